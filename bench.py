@@ -1,0 +1,158 @@
+#!/usr/bin/env python3
+"""Benchmark of the Spring-Ising hot path on one MI355X.
+
+Workload: the plain FP32 method on a K2000-shaped instance -- a complete
+graph of N = 2000 spins with iid +-1 couplings (seeded synthetic stand-in
+for the K2000 benchmark), R = 1024 replicas started at x0 ~ U(-0.1, 0.1) with
+zero momenta, 10000 iterations of Eq. (8) with the paper's linear zeta
+schedule (k = 0.5, Delta = 0.2, m = 1, zeta 0.04 -> 0.5, walls sqrt 2 / 2),
+then the int32 Ising energy of sign(q) for every replica.
+
+One benchmark step = one such full run (reset to x0, 10000 iterations,
+energy readout).  Reported value: spin-updates/s = N * R * iterations / s.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+N, R, ITERS = 2000, 1024, 10000
+# MI355X published peaks
+PEAK_FP32_MFMA_TFLOPS = 157.3
+PEAK_HBM_GBS = 8000.0
+
+
+def cpu_baseline(budget_s: float = 15.0):
+    """Time the FP64 oracle (as it stands) on a bounded sample of the same
+    workload on the host cores; extrapolate per iteration."""
+    import numpy as np
+
+    import oracle
+    from paper_2305_07187_amd import instances
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max((i.get("num_threads", 1) for i in threadpool_info()), default=os.cpu_count())
+    except Exception:
+        cores = os.cpu_count()
+    J = instances.make_pm1(N, 0).astype(np.float64)
+    Q = instances.make_x0(N, R, 0).T.astype(np.float64)
+    P = np.zeros_like(Q)
+    dt = oracle.dt_schedule(ITERS)
+    zeta = oracle.zeta_schedule(ITERS, float(np.float32(0.04)), float(np.float32(0.5)))
+    qmax = float(np.float32(np.sqrt(2.0)))
+    t0 = time.perf_counter()
+    done = 0
+    while done < ITERS and time.perf_counter() - t0 < budget_s:
+        Q, P = oracle.step(J, Q, P, float(dt[done]), float(zeta[done]), qmax=qmax)
+        done += 1
+    el = time.perf_counter() - t0
+    return {"value": N * R * done / el, "unit": "spin-updates/s", "cores": int(cores),
+            "kind": "oracle",
+            "sample": f"first {done} of {ITERS} iterations at N={N}, R={R} (FP64 NumPy, "
+                      f"{el:.1f} s), extrapolated per iteration"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--iters", type=int, default=ITERS, help=argparse.SUPPRESS)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the replica-"
+              "parallel path has no cross-GPU step to measure here.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2305_07187_amd import instances
+    from paper_2305_07187_amd import spring_ising as si
+
+    if not os.path.exists(si.LIB_PATH):
+        from paper_2305_07187_amd import build
+        build.build(verbose=False)
+    si.load_library()
+    dev = torch.device("cuda:0")
+    iters = args.iters
+    Jn = instances.make_pm1(N, 0)
+    J = torch.from_numpy(Jn).to(dev)
+    x0 = torch.from_numpy(instances.make_x0(N, R, 0)).to(dev)
+    model = si.SpringIsing(J, x0, total_steps=iters)
+    info = model.info()
+    stream = torch.cuda.current_stream()
+    W = float(-np.triu(Jn.astype(np.float64), 1).sum())
+
+    def one_run(ev=None):
+        model.set_state(x0, None, 0)
+        if ev is not None:
+            ev[0].record(stream)
+        model.run(iters)
+        if ev is not None:
+            ev[1].record(stream)
+        return model.energy()
+
+    for _ in range(args.warmup):
+        one_run()
+    torch.cuda.synchronize()
+
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    energies = None
+    for k in range(args.steps):
+        energies = one_run(evs[k])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    run_ms = [a.elapsed_time(b) for a, b in evs]
+    kernel_us = 1000.0 * sum(run_ms) / (len(run_ms) * iters)  # per step launch
+
+    e = energies.cpu().numpy().astype(np.float64)
+    cuts = (W - e) / 2
+    flops = 2.0 * N * N * R
+    achieved_tflops = flops / (kernel_us * 1e-6) / 1e12
+    value = N * R * iters * args.steps / elapsed
+    out = {
+        "metric": "spin-updates/s (N*R*steps/s) at N=2000",
+        "value": value,
+        "unit": "spin-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1000.0 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"K2000-shaped +-1 complete graph, N={N}, R={R} replicas, "
+                               f"{iters} iterations, paper linear zeta schedule, FP32",
+                   "n": N, "replicas": R, "iterations": iters, "precision": "fp32",
+                   "kernel": info["kernel_name"]},
+        "roofline": {"bound": "mfma", "achieved": achieved_tflops,
+                     "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved_tflops / PEAK_FP32_MFMA_TFLOPS, "traffic": None,
+                     "kernel": info["kernel_name"], "avg_launch_us": kernel_us,
+                     "algorithmic_flop_per_launch": flops},
+        "result": {"best_cut": float(cuts.max()), "mean_cut": float(cuts.mean()),
+                   "best_energy": int(e.min()), "mean_energy": float(e.mean())},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,194 @@
+/*
+ * spring_ising.h -- C ABI of the MI355X (gfx950) Spring-Ising hot path.
+ *
+ * The library iterates the Spring-Ising Algorithm of Jiang et al.,
+ * "Point convolutional neural network algorithm for Ising model ground state
+ * research based on spring vibration" (arXiv 2305.07187):
+ *
+ *   Ising energy, Eq. (1):   H = - sum_{i<j} J_ij s_i s_j - sum_i h_i s_i
+ *   iteration, Eq. (8) (Eq. (5) with the mass m kept):
+ *     q_i(n+1) = q_i(n) + (Delta_n/m) p_i(n)
+ *     p_i(n+1) = p_i(n) - Delta_n k q_i(n) + zeta_n Delta_n sum_j J_ij q_j(n) [+ zeta_n Delta_n h_i]
+ *   walls: q clamped to [-qmax, qmax] (Eq. 6, qmax = sqrt 2) and p to
+ *     [-pmax, pmax] (Methods, constraints of Eq. 8, pmax = 2);
+ *   zeta_n: piecewise-constant, linear in the iteration count
+ *     (Methods; Fig. 4 and Fig. 5 captions);
+ *   readout: s = sign(q) after the last step (Methods, hardware mapping).
+ *
+ * Many independent replicas run side by side; they are the pixels of the
+ * paper's point-convolution feature map (Fig. 3).  One step is a dense
+ * N x N by N x R product (the 1x1 convolution) fused with the update.
+ *
+ * Conventions for every entry point
+ *   - Every call returns si_status and never throws.  On failure a message
+ *     is available from spring_ising_last_error() (thread-local, valid until
+ *     the next call on the same thread).
+ *   - Array arguments are DEVICE pointers (e.g. a torch tensor's data_ptr())
+ *     unless marked "host".  Host memory passed where device memory is
+ *     required is rejected with SI_ERR_INVALID.
+ *   - All device work is ordered on the stream given to the init call; no
+ *     call synchronises the host except init (one validation round trip).
+ *     Outputs written to caller buffers are complete once that stream has
+ *     passed the call.
+ *   - Layouts are row-major, replica-major: x[r*N + i] is spin i of
+ *     replica r (channels-last feature map), J[i*N + j].
+ *   - A context is single-stream and not thread-safe; distinct contexts are
+ *     independent.  A HIP failure poisons the context: later calls other
+ *     than destroy return SI_ERR_STATE.
+ */
+#ifndef SPRING_ISING_H
+#define SPRING_ISING_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct si_ctx si_ctx; /* opaque; owns every device buffer it allocates */
+
+typedef enum {
+  SI_OK = 0,
+  SI_ERR_INVALID = -1,     /* bad argument or input (asymmetric J, host pointer, ...) */
+  SI_ERR_OOM = -2,         /* device allocation failed */
+  SI_ERR_HIP = -3,         /* a HIP call failed; the context is poisoned */
+  SI_ERR_STATE = -4,       /* context poisoned or not usable for this call */
+  SI_ERR_UNSUPPORTED = -5, /* valid request this build or input cannot serve */
+  SI_ERR_RANGE = -6        /* step index past the schedule length */
+} si_status;
+
+/* Update order.  PAPER: Eq. (8) as printed, both right-hand sides read the
+ * step-n state.  SYMPLECTIC: p first, then q moves with the new (clamped) p. */
+typedef enum { SI_ORDER_PAPER = 0, SI_ORDER_SYMPLECTIC = 1 } si_order;
+
+/* Wall model.  CLAMP: q and p clamped independently (Eq. 6 and the momentum
+ * box of Methods).  INELASTIC: additionally p = 0 wherever q ran past its
+ * wall (the perfectly inelastic wall that Methods refers to). */
+typedef enum { SI_WALL_CLAMP = 0, SI_WALL_INELASTIC = 1 } si_wall;
+
+/* Arithmetic of the coupling product J.Q (accumulation is always FP32).
+ *   FP32        : FP32 J and FP32 positions (plain method).
+ *   BF16X_FP8J  : J stored as FP8 e4m3 (must be exact, e.g. +-1), positions
+ *                 as a BF16 copy of the FP32 master state.
+ *   BF16X_BF16J : J stored as BF16 (must be exact), positions BF16.
+ *   BF16X_HILOJ : any real J split as hi = bf16(J), lo = bf16(J - hi),
+ *                 two BF16 products into one FP32 accumulator; positions BF16.
+ *   BF16X3_EXACTJ: J exact in BF16 (e.g. +-1); the FP32 positions split into
+ *                 three BF16 pieces whose sum is the FP32 value exactly, so
+ *                 every product is exact and only the FP32 accumulation
+ *                 rounds (FP32-equivalent, on the BF16 matrix cores).
+ * The master positions and momenta are FP32 in every mode. */
+typedef enum {
+  SI_PREC_FP32 = 0,
+  SI_PREC_BF16X_FP8J = 1,
+  SI_PREC_BF16X_BF16J = 2,
+  SI_PREC_BF16X_HILOJ = 3,
+  SI_PREC_BF16X3_EXACTJ = 4
+} si_precision;
+
+/* Scalar parameters.  spring_ising_default_params() fills the paper's values:
+ * k = 0.5, m = 1, dt = 0.2, zeta from 0.8*zeta0 = 0.04 to 10*zeta0 = 0.5
+ * (zeta0 = 0.05), stair_len = 1 (exactly linear), qmax = sqrt 2, pmax = 2
+ * (Fig. 4 and Fig. 5 captions, Eq. 6, Methods). */
+typedef struct {
+  float k;            /* spring constant (finite) */
+  float m;            /* mass, > 0 */
+  float dt;           /* time step Delta for the generated schedule, > 0 */
+  float zeta_start;   /* zeta at the first step */
+  float zeta_end;     /* zeta at the last stair */
+  int32_t total_steps;/* S, length of the schedules, >= 1 */
+  int32_t stair_len;  /* L >= 1: zeta constant over runs of L steps; 1 = linear */
+  float qmax;         /* position wall, > 0 */
+  float pmax;         /* momentum wall, > 0 */
+  int32_t order;      /* si_order */
+  int32_t wall;       /* si_wall */
+  int32_t precision;  /* si_precision */
+  int32_t tile;       /* 0 = automatic kernel choice; otherwise a tile id
+                         reported by spring_ising_info (tuning override) */
+} si_params;
+
+/* Read-only facts about a context (host struct). */
+typedef struct {
+  int32_t n, r;             /* problem size */
+  int32_t n_pad, r_pad;     /* padded device layout */
+  int32_t t;                /* steps taken so far */
+  int32_t total_steps;      /* schedule length S */
+  int32_t j_integer;        /* 1 if every J_ij is an integer with |J_ij| <= 127 */
+  int32_t j_fp8_exact;      /* 1 if every J_ij is exact in FP8 e4m3 */
+  int32_t j_bf16_exact;     /* 1 if every J_ij is exact in BF16 */
+  int32_t tile;             /* tile id of the step kernel in use */
+  int32_t precision;        /* si_precision in use */
+  int32_t graph_steps;      /* steps per captured HIP graph (0: not captured) */
+  int64_t device_bytes;     /* device memory owned by the context */
+  char kernel_name[64];     /* name of the step kernel in use */
+} si_info;
+
+/* Fill *prm (host) with the paper's parameter values and total_steps = S. */
+si_status spring_ising_default_params(si_params *prm, int32_t total_steps);
+
+/* Create a context for n spins and r replicas.
+ *   J  : device, n*n floats, row-major; must be symmetric with a zero
+ *        diagonal and finite (Eq. 1 sums over pairs i<j; the diagonal has no
+ *        meaning).  Violations -> SI_ERR_INVALID.  Precision modes that need
+ *        an exact J format reject other J with SI_ERR_UNSUPPORTED.
+ *   x0 : device, r*n floats, replica-major initial positions.
+ *   p0 : device, r*n floats, or NULL for zero initial momenta.
+ *   prm: host; copied.  Schedules Delta_n = prm->dt and zeta_n (linear in
+ *        stairs of prm->stair_len) are generated for prm->total_steps steps.
+ *   hip_stream: hipStream_t for all work of this context (NULL = null stream).
+ * The inputs are copied into library-owned, padded buffers; the caller may
+ * release them once the stream has passed this call.  Synchronises once. */
+si_status spring_ising_init(si_ctx **out, int32_t n, int32_t r, const float *J,
+                            const float *x0, const float *p0, const si_params *prm,
+                            void *hip_stream);
+
+/* Replace the per-step schedules (device, total_steps floats each).
+ * Delta_n must be > 0; values are not checked on the host. */
+si_status spring_ising_set_schedule(si_ctx *ctx, const float *dt, const float *zeta);
+
+/* Copy the per-step schedules out (device, total_steps floats each). */
+si_status spring_ising_get_schedule(si_ctx *ctx, float *dt, float *zeta);
+
+/* Set an external field h (device, n floats; Eq. 1).  It adds zeta_n h_i to
+ * the force of Eq. (4) and -sum_i h_i s_i to the energy.  NULL clears it. */
+si_status spring_ising_set_field(si_ctx *ctx, const float *h);
+
+/* One iteration of Eq. (8) with the walls at step index t; t += 1.
+ * SI_ERR_RANGE if t == total_steps. */
+si_status spring_ising_step(si_ctx *ctx);
+
+/* n_steps iterations (n_steps >= 0).  SI_ERR_RANGE, with nothing run, if
+ * t + n_steps > total_steps.  Asynchronous: no host round trip per step. */
+si_status spring_ising_run(si_ctx *ctx, int32_t n_steps);
+
+/* Readout: s[r*n + i] = +1 if q_i >= 0 (also -0.0), else -1 (device int8). */
+si_status spring_ising_spins(si_ctx *ctx, int8_t *s);
+
+/* Eq. (1) energy of the current spins s = sign(q), per replica.
+ *   e_int : device, r int32, or NULL.  Exact; needs integer J (|J_ij| <= 127)
+ *           and an integer field, else SI_ERR_UNSUPPORTED.
+ *   e_real: device, r doubles, or NULL.  For integer J it equals e_int; for
+ *           real J it is an FP32 product with a compensated FP32 sum. */
+si_status spring_ising_energy(si_ctx *ctx, int32_t *e_int, double *e_real);
+
+/* Copy the state out: x, p device r*n floats (either may be NULL); *t (host,
+ * may be NULL) receives the step index. */
+si_status spring_ising_get_state(si_ctx *ctx, float *x, float *p, int32_t *t);
+
+/* Overwrite the state: x, p device r*n floats (p may be NULL for zeros),
+ * 0 <= t <= total_steps.  Resuming from a saved state is bit-identical. */
+si_status spring_ising_set_state(si_ctx *ctx, const float *x, const float *p, int32_t t);
+
+/* Fill *info (host). */
+si_status spring_ising_info(si_ctx *ctx, si_info *info);
+
+/* Release every device buffer of the context (waits for its stream). */
+si_status spring_ising_destroy(si_ctx *ctx);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *spring_ising_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SPRING_ISING_H */

@@ -1,0 +1,155 @@
+// Readout and exact Ising energy (Eq. 1) on the int8 matrix cores.
+//
+// For integer couplings |J_ij| <= 127 the energy of s = sign(q) is exact:
+// G = J.S is an int8 x int8 product with int32 accumulation
+// (v_mfma_i32_16x16x32_i8), and sum_i s_i (G_i + 2 h_i) = 2 sum_{i<j} J_ij
+// s_i s_j + 2 sum_i h_i s_i is even, so E = -(that sum)/2 is exact.
+// Partial sums from all workgroups are combined with integer atomics, whose
+// result does not depend on their order.
+//
+// MFMA operand layout (one 16x16 block, K = 32): lane l supplies the 8 bytes
+// A[l%16][8(l/16) .. 8(l/16)+7] and B[8(l/16) .. +7][l%16]; D as for the FP32
+// shape.  Each lane reads 16 contiguous bytes per operand and per 64-byte
+// slab; MFMA s = 0, 1 uses bytes 8s .. 8s+7 of them (a permutation of the
+// contraction index applied identically to both operands).
+#include "si_internal.h"
+
+namespace si {
+
+typedef int intx4 __attribute__((ext_vector_type(4)));
+
+namespace {
+constexpr int EBM = 64, EBN = 64, EBK = 64, ELDK = EBK + 16;  // bytes
+constexpr int EWTM = 32, EWTN = 32;  // 2 x 2 waves
+}  // namespace
+
+__global__ __launch_bounds__(256) void energy_i8_kernel(const int8_t *__restrict__ J8,
+                                                        const int8_t *__restrict__ S8,
+                                                        const int8_t *__restrict__ h8,
+                                                        int32_t *__restrict__ acc_out, int ld) {
+  __shared__ __attribute__((aligned(16))) int8_t As[2][EBM * ELDK];
+  __shared__ __attribute__((aligned(16))) int8_t Bs[2][EBN * ELDK];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wy = wave >> 1, wx = wave & 1;
+  const int m0 = blockIdx.x * EBM, n0 = blockIdx.y * EBN;
+  const int lrow = lane & 15, lk = (lane >> 4) * 16;
+  // staging: each thread moves 16 bytes of A and 16 bytes of B per slab
+  const int srow = tid >> 2, sc = (tid & 3) * 16;
+
+  intx4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = intx4{0, 0, 0, 0};
+
+  const int nk = ld / EBK;
+  int4 ra = *reinterpret_cast<const int4 *>(J8 + (size_t)(m0 + srow) * ld + sc);
+  int4 rb = *reinterpret_cast<const int4 *>(S8 + (size_t)(n0 + srow) * ld + sc);
+  *reinterpret_cast<int4 *>(&As[0][srow * ELDK + sc]) = ra;
+  *reinterpret_cast<int4 *>(&Bs[0][srow * ELDK + sc]) = rb;
+  __syncthreads();
+  for (int kt = 0; kt < nk; ++kt) {
+    const int buf = kt & 1;
+    if (kt + 1 < nk) {
+      ra = *reinterpret_cast<const int4 *>(J8 + (size_t)(m0 + srow) * ld + (kt + 1) * EBK + sc);
+      rb = *reinterpret_cast<const int4 *>(S8 + (size_t)(n0 + srow) * ld + (kt + 1) * EBK + sc);
+    }
+    int4 a[2], b[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+      a[i] = *reinterpret_cast<const int4 *>(&As[buf][(wy * EWTM + i * 16 + lrow) * ELDK + lk]);
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+      b[j] = *reinterpret_cast<const int4 *>(&Bs[buf][(wx * EWTN + j * 16 + lrow) * ELDK + lk]);
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        long a0 = ((long)(uint32_t)a[i].y << 32) | (uint32_t)a[i].x;
+        long a1 = ((long)(uint32_t)a[i].w << 32) | (uint32_t)a[i].z;
+        long b0 = ((long)(uint32_t)b[j].y << 32) | (uint32_t)b[j].x;
+        long b1 = ((long)(uint32_t)b[j].w << 32) | (uint32_t)b[j].z;
+        acc[i][j] = __builtin_amdgcn_mfma_i32_16x16x32_i8(a0, b0, acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_i32_16x16x32_i8(a1, b1, acc[i][j], 0, 0, 0);
+      }
+    if (kt + 1 < nk) {
+      *reinterpret_cast<int4 *>(&As[buf ^ 1][srow * ELDK + sc]) = ra;
+      *reinterpret_cast<int4 *>(&Bs[buf ^ 1][srow * ELDK + sc]) = rb;
+    }
+    __syncthreads();
+  }
+
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int col = n0 + wx * EWTN + j * 16 + (lane & 15);
+    int c = 0;
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int row = m0 + wy * EWTM + i * 16 + (lane >> 4) * 4;
+      const char4 s4 = *reinterpret_cast<const char4 *>(S8 + (size_t)col * ld + row);
+      char4 h4 = make_char4(0, 0, 0, 0);
+      if (h8) h4 = *reinterpret_cast<const char4 *>(h8 + row);
+      c += (int)s4.x * (acc[i][j][0] + 2 * (int)h4.x);
+      c += (int)s4.y * (acc[i][j][1] + 2 * (int)h4.y);
+      c += (int)s4.z * (acc[i][j][2] + 2 * (int)h4.z);
+      c += (int)s4.w * (acc[i][j][3] + 2 * (int)h4.w);
+    }
+    c += __shfl_xor(c, 16);
+    c += __shfl_xor(c, 32);
+    if (lane < 16) atomicAdd(acc_out + col, c);
+  }
+}
+
+__global__ void sign_kernel(const float4 *__restrict__ q, char4 *__restrict__ s, int64_t n4) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n4;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const float4 v = q[i];
+    s[i] = make_char4(v.x < 0.f ? -1 : 1, v.y < 0.f ? -1 : 1, v.z < 0.f ? -1 : 1,
+                      v.w < 0.f ? -1 : 1);
+  }
+}
+
+__global__ void energy_i8_finalize_kernel(int32_t *acc, int r, int32_t *e_int, double *e_real) {
+  const int col = blockIdx.x * blockDim.x + threadIdx.x;
+  if (col >= r) return;
+  const int32_t e = -(acc[col] / 2);
+  if (e_int) e_int[col] = e;
+  if (e_real) e_real[col] = (double)e;
+  acc[col] = 0;  // ready for the next evaluation
+}
+
+__global__ void zero_i32_kernel(int32_t *p, int64_t count) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0;
+}
+
+hipError_t launch_sign(const float *q, int8_t *s8, int32_t n_pad, int32_t r_pad, hipStream_t s) {
+  const int64_t n4 = (int64_t)n_pad * r_pad / 4;
+  const int blocks = (int)((n4 + 255) / 256 < 4096 ? (n4 + 255) / 256 : 4096);
+  sign_kernel<<<blocks, 256, 0, s>>>(reinterpret_cast<const float4 *>(q),
+                                     reinterpret_cast<char4 *>(s8), n4);
+  return hipGetLastError();
+}
+
+hipError_t launch_energy_i8(const int8_t *J8, const int8_t *S8, const int8_t *h8, int32_t *acc,
+                            int32_t n_pad, int32_t r_pad, hipStream_t s) {
+  if (n_pad % EBM || r_pad % EBN) return hipErrorInvalidValue;
+  dim3 grid(n_pad / EBM, r_pad / EBN);
+  energy_i8_kernel<<<grid, 256, 0, s>>>(J8, S8, h8, acc, n_pad);
+  return hipGetLastError();
+}
+
+hipError_t launch_energy_i8_finalize(int32_t *acc, int32_t r, int32_t *e_int, double *e_real,
+                                     hipStream_t s) {
+  energy_i8_finalize_kernel<<<(r + 255) / 256, 256, 0, s>>>(acc, r, e_int, e_real);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_i32(int32_t *p, int64_t count, hipStream_t s) {
+  const int blocks = (int)((count + 255) / 256 < 1024 ? (count + 255) / 256 : 1024);
+  zero_i32_kernel<<<blocks > 0 ? blocks : 1, 256, 0, s>>>(p, count);
+  return hipGetLastError();
+}
+
+}  // namespace si

@@ -1,0 +1,84 @@
+// Internal declarations shared by the host runtime and the kernel files of
+// the Spring-Ising library.  Not part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "spring_ising.h"
+
+namespace si {
+
+// Tile ids of the FP32 step kernel (BM spins x BN replicas per workgroup).
+enum TileId : int32_t {
+  TILE_AUTO = 0,
+  TILE_F32_64x128 = 1,
+  TILE_F32_64x64 = 2,
+  TILE_F32_32x32 = 3,
+  TILE_F32_128x64 = 4,
+  TILE_F32_128x128 = 5,
+  TILE_F32_32x64 = 6,
+  TILE_F32_LAST = 6,
+};
+
+struct TileShape {
+  int32_t bm, bn;
+  const char *name;
+};
+TileShape tile_shape(int32_t tile);
+
+// Scalars of one step, shared by every step launcher.
+struct StepArgs {
+  const float *J;     // [n_pad][n_pad], zero padded, symmetric
+  const float *q_in;  // [r_pad][n_pad]
+  const float *p_in;
+  float *q_out;
+  float *p_out;
+  const float *dt;    // schedule arrays [S]
+  const float *zeta;
+  const float *h;     // field [n_pad] or nullptr
+  int32_t t;          // schedule index of this step
+  int32_t ld;         // n_pad
+  int32_t n_pad, r_pad;
+  float k, inv_m, qmax, pmax;
+  int32_t order;      // si_order
+  int32_t wall;       // si_wall
+};
+
+hipError_t launch_step_f32(int32_t tile, const StepArgs &a, hipStream_t s);
+
+// G = J.sign(Q) in FP32, per-row-tile partial sums of s_i (G_i + 2 h_i):
+// part[row_tile][r].  BM is fixed at 64 rows.
+hipError_t launch_energy_f32_partial(const float *J, const float *q, const float *h,
+                                     float *part, int32_t n_pad, int32_t r_pad,
+                                     hipStream_t s);
+hipError_t launch_energy_f32_finalize(const float *part, int32_t n_tiles, int32_t r,
+                                      int32_t r_pad, double *e_real, hipStream_t s);
+
+// Exact energy: s = sign(q) as int8 into S8, then G = J8.S8 on int8 MFMA,
+// acc[r] += sum_i s_i (G_i + 2 h_i), then e[r] = -acc[r]/2.
+hipError_t launch_sign(const float *q, int8_t *s8, int32_t n_pad, int32_t r_pad,
+                       hipStream_t s);
+hipError_t launch_energy_i8(const int8_t *J8, const int8_t *S8, const int8_t *h8,
+                            int32_t *acc, int32_t n_pad, int32_t r_pad, hipStream_t s);
+hipError_t launch_energy_i8_finalize(int32_t *acc, int32_t r, int32_t *e_int,
+                                     double *e_real, hipStream_t s);
+hipError_t launch_zero_i32(int32_t *p, int64_t count, hipStream_t s);
+
+// Layout conversion and validation.
+hipError_t launch_pack_matrix(const float *src, int32_t n, float *dst, int8_t *dst8,
+                              int32_t n_pad, hipStream_t s);
+hipError_t launch_pack_state(const float *src, int32_t n, int32_t r, float *dst,
+                             int32_t n_pad, int32_t r_pad, hipStream_t s);
+hipError_t launch_unpack_state(const float *src, int32_t n, int32_t r, float *dst,
+                               int32_t n_pad, hipStream_t s);
+hipError_t launch_unpack_spins(const int8_t *src, int32_t n, int32_t r, int8_t *dst,
+                               int32_t n_pad, hipStream_t s);
+hipError_t launch_pack_field(const float *h, int32_t n, float *hf, int8_t *h8,
+                             int32_t n_pad, int32_t *flags, hipStream_t s);
+
+// flags[0]: asymmetric, [1]: nonzero diagonal, [2]: non-finite,
+// [3]: non-integer or |J|>127, [4]: not FP8-e4m3 exact, [5]: not BF16 exact
+hipError_t launch_validate(const float *J, int32_t n, int32_t *flags, hipStream_t s);
+
+}  // namespace si

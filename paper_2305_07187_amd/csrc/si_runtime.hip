@@ -1,0 +1,456 @@
+// Host runtime of the Spring-Ising library: the C ABI declared in
+// include/spring_ising.h.  Owns the padded device buffers, builds the
+// zeta/Delta schedules, validates J, picks the step kernel and launches it.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+#include <string>
+#include <vector>
+
+#include "si_internal.h"
+
+using namespace si;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+si_status fail(si_status st, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return st;
+}
+
+int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+bool is_device_ptr(const void *p) {
+  if (!p) return false;
+  hipPointerAttribute_t attr;
+  memset(&attr, 0, sizeof attr);
+  hipError_t e = hipPointerGetAttributes(&attr, p);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return attr.type == hipMemoryTypeDevice || attr.type == hipMemoryTypeManaged;
+}
+
+// Piecewise-constant linear zeta(t_step): K = ceil(S/L) stairs, stair s of
+// step n is floor(n/L), zeta = zs + (ze - zs) * s / (K - 1) (zs alone when
+// K = 1).  Formed in double, rounded once to float.  Contraction is off so
+// the double expression rounds exactly as written.
+#pragma clang fp contract(off)
+void build_schedules(const si_params &p, std::vector<float> &dt, std::vector<float> &zeta) {
+  const int32_t S = p.total_steps, L = p.stair_len;
+  const int64_t K = (S + (int64_t)L - 1) / L;
+  dt.assign(S, p.dt);
+  zeta.resize(S);
+  const double zs = p.zeta_start, ze = p.zeta_end;
+  for (int32_t n = 0; n < S; ++n) {
+    const int64_t s = n / L;
+    double v;
+    if (K == 1)
+      v = zs;
+    else
+      v = zs + (ze - zs) * ((double)s / (double)(K - 1));
+    zeta[n] = (float)v;
+  }
+}
+
+}  // namespace
+
+struct si_ctx {
+  int32_t n = 0, r = 0, n_pad = 0, r_pad = 0;
+  si_params prm{};
+  hipStream_t stream = nullptr;
+  int device = 0;
+  int num_cus = 0;
+  int32_t tile = 0;
+  float *J = nullptr;
+  int8_t *J8 = nullptr;
+  float *q[2] = {nullptr, nullptr}, *p[2] = {nullptr, nullptr};
+  int cur = 0;
+  float *dt = nullptr, *zeta = nullptr;
+  float *hf = nullptr;
+  int8_t *h8 = nullptr;
+  bool has_field = false, field_integer = false;
+  int32_t field_maxabs = 0;
+  int8_t *S8 = nullptr;
+  int32_t *eacc = nullptr;
+  float *epart = nullptr;
+  int32_t *flags = nullptr;  // device validation flags [8]
+  int32_t hflags[8] = {0};
+  int32_t t = 0;
+  bool poisoned = false;
+  int64_t bytes = 0;
+  std::vector<void *> allocs;
+  std::vector<float> host_dt, host_zeta;  // kept alive for the async upload
+
+  template <class T>
+  hipError_t alloc(T **ptr, int64_t count) {
+    void *raw = nullptr;
+    hipError_t e = hipMalloc(&raw, (size_t)count * sizeof(T));
+    if (e != hipSuccess) return e;
+    allocs.push_back(raw);
+    bytes += count * (int64_t)sizeof(T);
+    *ptr = static_cast<T *>(raw);
+    return hipSuccess;
+  }
+  ~si_ctx() {
+    for (void *a : allocs) (void)hipFree(a);
+  }
+};
+
+#define SI_HIP(ctx, expr)                                                              \
+  do {                                                                                 \
+    hipError_t _e = (expr);                                                            \
+    if (_e != hipSuccess) {                                                            \
+      if (ctx) (ctx)->poisoned = true;                                                 \
+      return fail(_e == hipErrorOutOfMemory ? SI_ERR_OOM : SI_ERR_HIP, "%s: %s (%s)",  \
+                  __func__, hipGetErrorString(_e), #expr);                             \
+    }                                                                                  \
+  } while (0)
+
+#define SI_USABLE(ctx)                                                                 \
+  do {                                                                                 \
+    if (!(ctx)) return fail(SI_ERR_INVALID, "%s: null context", __func__);             \
+    if ((ctx)->poisoned)                                                               \
+      return fail(SI_ERR_STATE, "%s: context poisoned by an earlier HIP failure",      \
+                  __func__);                                                           \
+  } while (0)
+
+static si_status check_params(const si_params *p) {
+  if (!p) return fail(SI_ERR_INVALID, "params: null");
+  if (p->total_steps < 1) return fail(SI_ERR_INVALID, "params: total_steps must be >= 1");
+  if (p->stair_len < 1) return fail(SI_ERR_INVALID, "params: stair_len must be >= 1");
+  if (!(p->m > 0.f) || !isfinite(p->m)) return fail(SI_ERR_INVALID, "params: m must be > 0");
+  if (!(p->dt > 0.f) || !isfinite(p->dt)) return fail(SI_ERR_INVALID, "params: dt must be > 0");
+  if (!(p->qmax > 0.f) || !isfinite(p->qmax))
+    return fail(SI_ERR_INVALID, "params: qmax must be > 0");
+  if (!(p->pmax > 0.f) || !isfinite(p->pmax))
+    return fail(SI_ERR_INVALID, "params: pmax must be > 0");
+  if (!isfinite(p->k) || !isfinite(p->zeta_start) || !isfinite(p->zeta_end))
+    return fail(SI_ERR_INVALID, "params: k and zeta must be finite");
+  if (p->order != SI_ORDER_PAPER && p->order != SI_ORDER_SYMPLECTIC)
+    return fail(SI_ERR_INVALID, "params: unknown order %d", p->order);
+  if (p->wall != SI_WALL_CLAMP && p->wall != SI_WALL_INELASTIC)
+    return fail(SI_ERR_INVALID, "params: unknown wall %d", p->wall);
+  if (p->precision < SI_PREC_FP32 || p->precision > SI_PREC_BF16X3_EXACTJ)
+    return fail(SI_ERR_INVALID, "params: unknown precision %d", p->precision);
+  if (p->tile < 0 || p->tile > TILE_F32_LAST)
+    return fail(SI_ERR_INVALID, "params: unknown tile %d", p->tile);
+  return SI_OK;
+}
+
+// Largest-work tile that still gives at least one workgroup per CU; with no
+// such tile, the one with the most workgroups (small problems).
+static int32_t choose_tile(int32_t n, int32_t r, int num_cus) {
+  const int32_t order[] = {TILE_F32_64x128, TILE_F32_128x64, TILE_F32_64x64, TILE_F32_32x64,
+                           TILE_F32_32x32};
+  int32_t best = TILE_F32_32x32;
+  int64_t best_tiles = -1;
+  for (int32_t t : order) {
+    TileShape ts = tile_shape(t);
+    const int64_t np = round_up(n, ts.bm > 64 ? ts.bm : 64);
+    const int64_t rp = round_up(r, ts.bn > 64 ? ts.bn : 64);
+    const int64_t tiles = (np / ts.bm) * (rp / ts.bn);
+    if (tiles >= num_cus) return t;
+    if (tiles > best_tiles) {
+      best_tiles = tiles;
+      best = t;
+    }
+  }
+  return best;
+}
+
+extern "C" {
+
+const char *spring_ising_last_error(void) { return g_last_error.c_str(); }
+
+si_status spring_ising_default_params(si_params *prm, int32_t total_steps) {
+  if (!prm) return fail(SI_ERR_INVALID, "default_params: null");
+  memset(prm, 0, sizeof *prm);
+  prm->k = 0.5f;
+  prm->m = 1.0f;
+  prm->dt = 0.2f;
+  prm->zeta_start = 0.04f;  // 0.8 * zeta0, zeta0 = 0.05
+  prm->zeta_end = 0.5f;     // 10 * zeta0
+  prm->total_steps = total_steps;
+  prm->stair_len = 1;
+  prm->qmax = sqrtf(2.0f);
+  prm->pmax = 2.0f;
+  prm->order = SI_ORDER_PAPER;
+  prm->wall = SI_WALL_CLAMP;
+  prm->precision = SI_PREC_FP32;
+  prm->tile = 0;
+  if (total_steps < 1) return fail(SI_ERR_INVALID, "default_params: total_steps must be >= 1");
+  return SI_OK;
+}
+
+si_status spring_ising_init(si_ctx **out, int32_t n, int32_t r, const float *J, const float *x0,
+                            const float *p0, const si_params *prm, void *hip_stream) {
+  if (!out) return fail(SI_ERR_INVALID, "init: out is null");
+  *out = nullptr;
+  if (n < 1 || r < 1) return fail(SI_ERR_INVALID, "init: n=%d r=%d must be >= 1", n, r);
+  if (n > 65536 || r > (1 << 24))
+    return fail(SI_ERR_INVALID, "init: n=%d r=%d beyond the supported range", n, r);
+  if (!J || !x0) return fail(SI_ERR_INVALID, "init: J and x0 are required");
+  si_status st = check_params(prm);
+  if (st != SI_OK) return st;
+  if (prm->precision != SI_PREC_FP32)
+    return fail(SI_ERR_UNSUPPORTED, "init: precision %d is not available in this build",
+                prm->precision);
+  if (!is_device_ptr(J) || !is_device_ptr(x0) || (p0 && !is_device_ptr(p0)))
+    return fail(SI_ERR_INVALID, "init: J, x0 and p0 must be device pointers");
+
+  si_ctx *c = new (std::nothrow) si_ctx();
+  if (!c) return fail(SI_ERR_OOM, "init: host allocation failed");
+  c->n = n;
+  c->r = r;
+  c->prm = *prm;
+  c->stream = static_cast<hipStream_t>(hip_stream);
+#define INIT_HIP(expr)                                                                  \
+  do {                                                                                  \
+    hipError_t _e = (expr);                                                             \
+    if (_e != hipSuccess) {                                                             \
+      delete c;                                                                         \
+      return fail(_e == hipErrorOutOfMemory ? SI_ERR_OOM : SI_ERR_HIP, "init: %s (%s)", \
+                  hipGetErrorString(_e), #expr);                                        \
+    }                                                                                   \
+  } while (0)
+  INIT_HIP(hipGetDevice(&c->device));
+  INIT_HIP(hipDeviceGetAttribute(&c->num_cus, hipDeviceAttributeMultiprocessorCount, c->device));
+
+  c->tile = prm->tile ? prm->tile : choose_tile(n, r, c->num_cus);
+  const TileShape ts = tile_shape(c->tile);
+  c->n_pad = (int32_t)round_up(n, ts.bm > 64 ? ts.bm : 64);
+  c->r_pad = (int32_t)round_up(r, ts.bn > 64 ? ts.bn : 64);
+
+  // validation of J: one host round trip
+  INIT_HIP(c->alloc(&c->flags, 8));
+  INIT_HIP(launch_zero_i32(c->flags, 8, c->stream));
+  INIT_HIP(launch_validate(J, n, c->flags, c->stream));
+  INIT_HIP(hipMemcpyAsync(c->hflags, c->flags, sizeof c->hflags, hipMemcpyDeviceToHost,
+                          c->stream));
+  INIT_HIP(hipStreamSynchronize(c->stream));
+  if (c->hflags[0] || c->hflags[1] || c->hflags[2]) {
+    const int a = c->hflags[0], d = c->hflags[1], f = c->hflags[2];
+    delete c;
+    return fail(SI_ERR_INVALID, "init: J must be finite, symmetric with a zero diagonal "
+                "(asymmetric=%d nonzero_diagonal=%d nonfinite=%d)", a, d, f);
+  }
+  const bool j_integer = c->hflags[3] == 0;
+
+  const int64_t nn = (int64_t)c->n_pad * c->n_pad;
+  const int64_t nr = (int64_t)c->n_pad * c->r_pad;
+  INIT_HIP(c->alloc(&c->J, nn));
+  if (j_integer) INIT_HIP(c->alloc(&c->J8, nn));
+  for (int b = 0; b < 2; ++b) {
+    INIT_HIP(c->alloc(&c->q[b], nr));
+    INIT_HIP(c->alloc(&c->p[b], nr));
+  }
+  INIT_HIP(c->alloc(&c->dt, prm->total_steps));
+  INIT_HIP(c->alloc(&c->zeta, prm->total_steps));
+  INIT_HIP(c->alloc(&c->S8, nr));
+  INIT_HIP(c->alloc(&c->eacc, c->r_pad));
+  INIT_HIP(c->alloc(&c->epart, (int64_t)(c->n_pad / 64) * c->r_pad));
+
+  INIT_HIP(launch_pack_matrix(J, n, c->J, c->J8, c->n_pad, c->stream));
+  INIT_HIP(launch_pack_state(x0, n, r, c->q[0], c->n_pad, c->r_pad, c->stream));
+  INIT_HIP(launch_pack_state(p0, n, r, c->p[0], c->n_pad, c->r_pad, c->stream));
+  INIT_HIP(launch_zero_i32(c->eacc, c->r_pad, c->stream));
+  build_schedules(*prm, c->host_dt, c->host_zeta);
+  INIT_HIP(hipMemcpyAsync(c->dt, c->host_dt.data(), sizeof(float) * prm->total_steps,
+                          hipMemcpyHostToDevice, c->stream));
+  INIT_HIP(hipMemcpyAsync(c->zeta, c->host_zeta.data(), sizeof(float) * prm->total_steps,
+                          hipMemcpyHostToDevice, c->stream));
+#undef INIT_HIP
+  c->cur = 0;
+  c->t = 0;
+  *out = c;
+  return SI_OK;
+}
+
+si_status spring_ising_set_schedule(si_ctx *c, const float *dt, const float *zeta) {
+  SI_USABLE(c);
+  if (!is_device_ptr(dt) || !is_device_ptr(zeta))
+    return fail(SI_ERR_INVALID, "set_schedule: dt and zeta must be device pointers");
+  const size_t bytes = sizeof(float) * c->prm.total_steps;
+  SI_HIP(c, hipMemcpyAsync(c->dt, dt, bytes, hipMemcpyDeviceToDevice, c->stream));
+  SI_HIP(c, hipMemcpyAsync(c->zeta, zeta, bytes, hipMemcpyDeviceToDevice, c->stream));
+  return SI_OK;
+}
+
+si_status spring_ising_get_schedule(si_ctx *c, float *dt, float *zeta) {
+  SI_USABLE(c);
+  if ((dt && !is_device_ptr(dt)) || (zeta && !is_device_ptr(zeta)))
+    return fail(SI_ERR_INVALID, "get_schedule: outputs must be device pointers");
+  const size_t bytes = sizeof(float) * c->prm.total_steps;
+  if (dt) SI_HIP(c, hipMemcpyAsync(dt, c->dt, bytes, hipMemcpyDeviceToDevice, c->stream));
+  if (zeta) SI_HIP(c, hipMemcpyAsync(zeta, c->zeta, bytes, hipMemcpyDeviceToDevice, c->stream));
+  return SI_OK;
+}
+
+si_status spring_ising_set_field(si_ctx *c, const float *h) {
+  SI_USABLE(c);
+  if (!h) {
+    c->has_field = false;
+    return SI_OK;
+  }
+  if (!is_device_ptr(h)) return fail(SI_ERR_INVALID, "set_field: h must be a device pointer");
+  if (!c->hf) {
+    SI_HIP(c, c->alloc(&c->hf, c->n_pad));
+    SI_HIP(c, c->alloc(&c->h8, c->n_pad));
+  }
+  int32_t *fl = c->flags;
+  SI_HIP(c, launch_zero_i32(fl, 8, c->stream));
+  SI_HIP(c, launch_pack_field(h, c->n, c->hf, c->h8, c->n_pad, fl, c->stream));
+  int32_t hfl[8];
+  SI_HIP(c, hipMemcpyAsync(hfl, fl, sizeof hfl, hipMemcpyDeviceToHost, c->stream));
+  SI_HIP(c, hipStreamSynchronize(c->stream));
+  if (hfl[2]) return fail(SI_ERR_INVALID, "set_field: h must be finite");
+  c->has_field = true;
+  c->field_integer = hfl[3] == 0;
+  c->field_maxabs = hfl[6];
+  return SI_OK;
+}
+
+static si_status do_steps(si_ctx *c, int32_t n_steps) {
+  StepArgs a;
+  a.J = c->J;
+  a.dt = c->dt;
+  a.zeta = c->zeta;
+  a.h = c->has_field ? c->hf : nullptr;
+  a.ld = c->n_pad;
+  a.n_pad = c->n_pad;
+  a.r_pad = c->r_pad;
+  a.k = c->prm.k;
+  a.inv_m = 1.0f / c->prm.m;
+  a.qmax = c->prm.qmax;
+  a.pmax = c->prm.pmax;
+  a.order = c->prm.order;
+  a.wall = c->prm.wall;
+  for (int32_t s = 0; s < n_steps; ++s) {
+    a.q_in = c->q[c->cur];
+    a.p_in = c->p[c->cur];
+    a.q_out = c->q[c->cur ^ 1];
+    a.p_out = c->p[c->cur ^ 1];
+    a.t = c->t;
+    SI_HIP(c, launch_step_f32(c->tile, a, c->stream));
+    c->cur ^= 1;
+    c->t += 1;
+  }
+  return SI_OK;
+}
+
+si_status spring_ising_step(si_ctx *c) {
+  SI_USABLE(c);
+  if (c->t >= c->prm.total_steps)
+    return fail(SI_ERR_RANGE, "step: t=%d reached total_steps=%d", c->t, c->prm.total_steps);
+  return do_steps(c, 1);
+}
+
+si_status spring_ising_run(si_ctx *c, int32_t n_steps) {
+  SI_USABLE(c);
+  if (n_steps < 0) return fail(SI_ERR_INVALID, "run: n_steps=%d < 0", n_steps);
+  if ((int64_t)c->t + n_steps > c->prm.total_steps)
+    return fail(SI_ERR_RANGE, "run: t=%d + n_steps=%d exceeds total_steps=%d", c->t, n_steps,
+                c->prm.total_steps);
+  return do_steps(c, n_steps);
+}
+
+si_status spring_ising_spins(si_ctx *c, int8_t *s) {
+  SI_USABLE(c);
+  if (!is_device_ptr(s)) return fail(SI_ERR_INVALID, "spins: s must be a device pointer");
+  SI_HIP(c, launch_sign(c->q[c->cur], c->S8, c->n_pad, c->r_pad, c->stream));
+  SI_HIP(c, launch_unpack_spins(c->S8, c->n, c->r, s, c->n_pad, c->stream));
+  return SI_OK;
+}
+
+si_status spring_ising_energy(si_ctx *c, int32_t *e_int, double *e_real) {
+  SI_USABLE(c);
+  if ((e_int && !is_device_ptr(e_int)) || (e_real && !is_device_ptr(e_real)))
+    return fail(SI_ERR_INVALID, "energy: outputs must be device pointers");
+  if (!e_int && !e_real) return SI_OK;
+  // exact int32 path: integer J (and field) with a sum that cannot overflow
+  const int64_t jmax = c->hflags[6];
+  const int64_t bound = (int64_t)c->n * c->n * jmax +
+                        (c->has_field ? 2 * (int64_t)c->n * c->field_maxabs : 0);
+  const bool exact = c->J8 && (!c->has_field || c->field_integer) && bound < (1LL << 31);
+  if (e_int && !exact)
+    return fail(SI_ERR_UNSUPPORTED,
+                "energy: exact int32 energy needs integer |J_ij| <= 127 (and integer field)");
+  const int8_t *h8 = c->has_field ? c->h8 : nullptr;
+  if (exact) {
+    SI_HIP(c, launch_sign(c->q[c->cur], c->S8, c->n_pad, c->r_pad, c->stream));
+    SI_HIP(c, launch_energy_i8(c->J8, c->S8, h8, c->eacc, c->n_pad, c->r_pad, c->stream));
+    SI_HIP(c, launch_energy_i8_finalize(c->eacc, c->r, e_int, e_real, c->stream));
+  } else {
+    const float *hf = c->has_field ? c->hf : nullptr;
+    SI_HIP(c, launch_energy_f32_partial(c->J, c->q[c->cur], hf, c->epart, c->n_pad, c->r_pad,
+                                        c->stream));
+    SI_HIP(c, launch_energy_f32_finalize(c->epart, c->n_pad / 64, c->r, c->r_pad, e_real,
+                                         c->stream));
+  }
+  return SI_OK;
+}
+
+si_status spring_ising_get_state(si_ctx *c, float *x, float *p, int32_t *t) {
+  SI_USABLE(c);
+  if ((x && !is_device_ptr(x)) || (p && !is_device_ptr(p)))
+    return fail(SI_ERR_INVALID, "get_state: x and p must be device pointers");
+  if (x) SI_HIP(c, launch_unpack_state(c->q[c->cur], c->n, c->r, x, c->n_pad, c->stream));
+  if (p) SI_HIP(c, launch_unpack_state(c->p[c->cur], c->n, c->r, p, c->n_pad, c->stream));
+  if (t) *t = c->t;
+  return SI_OK;
+}
+
+si_status spring_ising_set_state(si_ctx *c, const float *x, const float *p, int32_t t) {
+  SI_USABLE(c);
+  if (!x) return fail(SI_ERR_INVALID, "set_state: x is required");
+  if (!is_device_ptr(x) || (p && !is_device_ptr(p)))
+    return fail(SI_ERR_INVALID, "set_state: x and p must be device pointers");
+  if (t < 0 || t > c->prm.total_steps)
+    return fail(SI_ERR_RANGE, "set_state: t=%d outside [0, %d]", t, c->prm.total_steps);
+  SI_HIP(c, launch_pack_state(x, c->n, c->r, c->q[c->cur], c->n_pad, c->r_pad, c->stream));
+  SI_HIP(c, launch_pack_state(p, c->n, c->r, c->p[c->cur], c->n_pad, c->r_pad, c->stream));
+  c->t = t;
+  return SI_OK;
+}
+
+si_status spring_ising_info(si_ctx *c, si_info *info) {
+  if (!c || !info) return fail(SI_ERR_INVALID, "info: null argument");
+  memset(info, 0, sizeof *info);
+  info->n = c->n;
+  info->r = c->r;
+  info->n_pad = c->n_pad;
+  info->r_pad = c->r_pad;
+  info->t = c->t;
+  info->total_steps = c->prm.total_steps;
+  info->j_integer = c->J8 != nullptr;
+  info->j_fp8_exact = c->hflags[4] == 0;
+  info->j_bf16_exact = c->hflags[5] == 0;
+  info->tile = c->tile;
+  info->precision = c->prm.precision;
+  info->graph_steps = 0;
+  info->device_bytes = c->bytes;
+  snprintf(info->kernel_name, sizeof info->kernel_name, "%s", tile_shape(c->tile).name);
+  return SI_OK;
+}
+
+si_status spring_ising_destroy(si_ctx *c) {
+  if (!c) return SI_OK;
+  hipError_t e = hipStreamSynchronize(c->stream);
+  delete c;
+  if (e != hipSuccess) return fail(SI_ERR_HIP, "destroy: %s", hipGetErrorString(e));
+  return SI_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,313 @@
+"""Python binding of the Spring-Ising C ABI (include/spring_ising.h).
+
+Argument marshalling only: every function below forwards to the entry point
+of the same name in libspring_ising.so, passing device pointers of torch
+tensors and the current HIP stream.  No step of the method runs in Python;
+if the library is missing, loading fails loudly.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libspring_ising.so")
+
+SI_OK = 0
+SI_ERR_INVALID = -1
+SI_ERR_OOM = -2
+SI_ERR_HIP = -3
+SI_ERR_STATE = -4
+SI_ERR_UNSUPPORTED = -5
+SI_ERR_RANGE = -6
+STATUS_NAMES = {0: "SI_OK", -1: "SI_ERR_INVALID", -2: "SI_ERR_OOM", -3: "SI_ERR_HIP",
+                -4: "SI_ERR_STATE", -5: "SI_ERR_UNSUPPORTED", -6: "SI_ERR_RANGE"}
+
+SI_ORDER_PAPER, SI_ORDER_SYMPLECTIC = 0, 1
+SI_WALL_CLAMP, SI_WALL_INELASTIC = 0, 1
+SI_PREC_FP32 = 0
+SI_PREC_BF16X_FP8J = 1
+SI_PREC_BF16X_BF16J = 2
+SI_PREC_BF16X_HILOJ = 3
+SI_PREC_BF16X3_EXACTJ = 4
+PRECISIONS = {"fp32": 0, "bf16x_fp8j": 1, "bf16x_bf16j": 2, "bf16x_hiloj": 3, "bf16x3_exactj": 4}
+
+
+class si_params(ctypes.Structure):
+    _fields_ = [
+        ("k", ctypes.c_float), ("m", ctypes.c_float), ("dt", ctypes.c_float),
+        ("zeta_start", ctypes.c_float), ("zeta_end", ctypes.c_float),
+        ("total_steps", ctypes.c_int32), ("stair_len", ctypes.c_int32),
+        ("qmax", ctypes.c_float), ("pmax", ctypes.c_float),
+        ("order", ctypes.c_int32), ("wall", ctypes.c_int32),
+        ("precision", ctypes.c_int32), ("tile", ctypes.c_int32),
+    ]
+
+
+class si_info(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int32), ("r", ctypes.c_int32),
+        ("n_pad", ctypes.c_int32), ("r_pad", ctypes.c_int32),
+        ("t", ctypes.c_int32), ("total_steps", ctypes.c_int32),
+        ("j_integer", ctypes.c_int32), ("j_fp8_exact", ctypes.c_int32),
+        ("j_bf16_exact", ctypes.c_int32), ("tile", ctypes.c_int32),
+        ("precision", ctypes.c_int32), ("graph_steps", ctypes.c_int32),
+        ("device_bytes", ctypes.c_int64), ("kernel_name", ctypes.c_char * 64),
+    ]
+
+    def as_dict(self):
+        d = {name: getattr(self, name) for name, _ in self._fields_}
+        d["kernel_name"] = self.kernel_name.decode()
+        return d
+
+
+class SpringIsingError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+        self.message = message
+
+
+_lib = None
+_P = ctypes.c_void_p
+_I = ctypes.c_int32
+
+_SIGNATURES = {
+    "spring_ising_default_params": [ctypes.POINTER(si_params), _I],
+    "spring_ising_init": [ctypes.POINTER(_P), _I, _I, _P, _P, _P, ctypes.POINTER(si_params), _P],
+    "spring_ising_set_schedule": [_P, _P, _P],
+    "spring_ising_get_schedule": [_P, _P, _P],
+    "spring_ising_set_field": [_P, _P],
+    "spring_ising_step": [_P],
+    "spring_ising_run": [_P, _I],
+    "spring_ising_spins": [_P, _P],
+    "spring_ising_energy": [_P, _P, _P],
+    "spring_ising_get_state": [_P, _P, _P, ctypes.POINTER(_I)],
+    "spring_ising_set_state": [_P, _P, _P, _I],
+    "spring_ising_info": [_P, ctypes.POINTER(si_info)],
+    "spring_ising_destroy": [_P],
+}
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libspring_ising.so (once).  Raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with "
+                           "`python -m paper_2305_07187_amd.build` (no fallback exists)")
+    lib = ctypes.CDLL(path)
+    for name, args in _SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
+    lib.spring_ising_last_error.argtypes = []
+    lib.spring_ising_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def last_error() -> str:
+    return load_library().spring_ising_last_error().decode()
+
+
+def _check(status: int):
+    if status != SI_OK:
+        raise SpringIsingError(status, last_error())
+
+
+def _ptr(t, dtype=None, numel=None, name="tensor"):
+    """Device pointer of a contiguous CUDA tensor (None -> NULL)."""
+    if t is None:
+        return None
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must live on the GPU")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} must have {numel} elements, got {t.numel()}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+# ---------------------------------------------------------------- C-ABI mirrors
+def spring_ising_default_params(total_steps: int) -> si_params:
+    p = si_params()
+    _check(load_library().spring_ising_default_params(ctypes.byref(p), int(total_steps)))
+    return p
+
+
+def spring_ising_init(n, r, J, x0, p0=None, params=None, stream=None):
+    import torch
+    lib = load_library()
+    if params is None:
+        raise ValueError("params required (spring_ising_default_params)")
+    ctx = ctypes.c_void_p()
+    st = lib.spring_ising_init(ctypes.byref(ctx), int(n), int(r),
+                               _ptr(J, torch.float32, n * n, "J"),
+                               _ptr(x0, torch.float32, n * r, "x0"),
+                               _ptr(p0, torch.float32, n * r, "p0"),
+                               ctypes.byref(params), stream if stream is not None else _stream())
+    _check(st)
+    return ctx
+
+
+def spring_ising_set_schedule(ctx, dt, zeta):
+    import torch
+    _check(load_library().spring_ising_set_schedule(ctx, _ptr(dt, torch.float32, name="dt"),
+                                                    _ptr(zeta, torch.float32, name="zeta")))
+
+
+def spring_ising_get_schedule(ctx, dt, zeta):
+    import torch
+    _check(load_library().spring_ising_get_schedule(ctx, _ptr(dt, torch.float32, name="dt"),
+                                                    _ptr(zeta, torch.float32, name="zeta")))
+
+
+def spring_ising_set_field(ctx, h):
+    import torch
+    _check(load_library().spring_ising_set_field(ctx, _ptr(h, torch.float32, name="h")))
+
+
+def spring_ising_step(ctx):
+    _check(load_library().spring_ising_step(ctx))
+
+
+def spring_ising_run(ctx, n_steps):
+    _check(load_library().spring_ising_run(ctx, int(n_steps)))
+
+
+def spring_ising_spins(ctx, s):
+    import torch
+    _check(load_library().spring_ising_spins(ctx, _ptr(s, torch.int8, name="s")))
+
+
+def spring_ising_energy(ctx, e_int=None, e_real=None):
+    import torch
+    _check(load_library().spring_ising_energy(ctx, _ptr(e_int, torch.int32, name="e_int"),
+                                              _ptr(e_real, torch.float64, name="e_real")))
+
+
+def spring_ising_get_state(ctx, x=None, p=None):
+    import torch
+    t = ctypes.c_int32()
+    _check(load_library().spring_ising_get_state(ctx, _ptr(x, torch.float32, name="x"),
+                                                 _ptr(p, torch.float32, name="p"),
+                                                 ctypes.byref(t)))
+    return t.value
+
+
+def spring_ising_set_state(ctx, x, p=None, t=0):
+    import torch
+    _check(load_library().spring_ising_set_state(ctx, _ptr(x, torch.float32, name="x"),
+                                                 _ptr(p, torch.float32, name="p"), int(t)))
+
+
+def spring_ising_info(ctx) -> dict:
+    info = si_info()
+    _check(load_library().spring_ising_info(ctx, ctypes.byref(info)))
+    return info.as_dict()
+
+
+def spring_ising_destroy(ctx):
+    _check(load_library().spring_ising_destroy(ctx))
+
+
+# ------------------------------------------------------------ convenience
+class SpringIsing:
+    """Owns one context; torch tensors carry inputs and outputs.
+
+    J: [N, N] float32 CUDA tensor; x0: [R, N]; p0: [R, N] or None.
+    """
+
+    def __init__(self, J, x0, p0=None, total_steps=1000, *, precision="fp32", order="paper",
+                 wall="clamp", tile=0, **overrides):
+        import torch
+        self.n = int(J.shape[0])
+        self.r = int(x0.shape[0])
+        prm = spring_ising_default_params(total_steps)
+        prm.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        prm.order = {"paper": 0, "symplectic": 1}[order] if isinstance(order, str) else int(order)
+        prm.wall = {"clamp": 0, "inelastic": 1}[wall] if isinstance(wall, str) else int(wall)
+        prm.tile = int(tile)
+        for key, val in overrides.items():
+            if not hasattr(prm, key):
+                raise KeyError(key)
+            setattr(prm, key, val)
+        self.params = prm
+        self.total_steps = int(prm.total_steps)
+        self.device = J.device
+        self._keep = (J.contiguous(), x0.contiguous(), None if p0 is None else p0.contiguous())
+        self.ctx = spring_ising_init(self.n, self.r, self._keep[0], self._keep[1], self._keep[2],
+                                     prm)
+        torch.cuda.current_stream().synchronize()
+        self._keep = None
+
+    def close(self):
+        if self.ctx is not None:
+            spring_ising_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self):
+        spring_ising_step(self.ctx)
+
+    def run(self, n_steps):
+        spring_ising_run(self.ctx, n_steps)
+
+    def state(self):
+        import torch
+        x = torch.empty(self.r, self.n, dtype=torch.float32, device=self.device)
+        p = torch.empty_like(x)
+        t = spring_ising_get_state(self.ctx, x, p)
+        return x, p, t
+
+    def set_state(self, x, p=None, t=0):
+        spring_ising_set_state(self.ctx, x.contiguous(), None if p is None else p.contiguous(), t)
+
+    def spins(self):
+        import torch
+        s = torch.empty(self.r, self.n, dtype=torch.int8, device=self.device)
+        spring_ising_spins(self.ctx, s)
+        return s
+
+    def energy(self, exact=True):
+        import torch
+        e_real = torch.empty(self.r, dtype=torch.float64, device=self.device)
+        if exact:
+            e_int = torch.empty(self.r, dtype=torch.int32, device=self.device)
+            spring_ising_energy(self.ctx, e_int, e_real)
+            return e_int
+        spring_ising_energy(self.ctx, None, e_real)
+        return e_real
+
+    def schedule(self):
+        import torch
+        dt = torch.empty(self.total_steps, dtype=torch.float32, device=self.device)
+        zeta = torch.empty_like(dt)
+        spring_ising_get_schedule(self.ctx, dt, zeta)
+        return dt, zeta
+
+    def set_schedule(self, dt, zeta):
+        spring_ising_set_schedule(self.ctx, dt.contiguous(), zeta.contiguous())
+
+    def set_field(self, h):
+        spring_ising_set_field(self.ctx, None if h is None else h.contiguous())
+
+    def info(self):
+        return spring_ising_info(self.ctx)
