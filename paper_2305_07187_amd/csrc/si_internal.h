@@ -9,17 +9,10 @@
 
 namespace si {
 
-// Tile ids of the FP32 step kernel (BM spins x BN replicas per workgroup).
-enum TileId : int32_t {
-  TILE_AUTO = 0,
-  TILE_F32_64x128 = 1,
-  TILE_F32_64x64 = 2,
-  TILE_F32_32x32 = 3,
-  TILE_F32_128x64 = 4,
-  TILE_F32_128x128 = 5,
-  TILE_F32_32x64 = 6,
-  TILE_F32_LAST = 6,
-};
+// Tile ids of the FP32 step kernel (see the tile table in si_step_f32.hip);
+// 0 selects automatically.
+constexpr int32_t TILE_AUTO = 0;
+constexpr int32_t TILE_F32_LAST = 12;
 
 struct TileShape {
   int32_t bm, bn;
@@ -46,6 +39,28 @@ struct StepArgs {
 };
 
 hipError_t launch_step_f32(int32_t tile, const StepArgs &a, hipStream_t s);
+
+// Step on the BF16 matrix cores (precision forms).
+constexpr int32_t TILE_BF16_LAST = 6;
+TileShape tile_shape_bf16(int32_t tile);
+struct BStepArgs {
+  const void *Ja;         // J plane: bf16 or fp8 [n_pad][n_pad]
+  const void *Jb;         // second J plane (lo of hi/lo) or nullptr
+  const uint16_t *qb_in;  // BF16 plane(s) of q, plane stride plane_stride
+  uint16_t *qb_out;
+  int64_t plane_stride;   // n_pad * r_pad
+  const float *q_in, *p_in;
+  float *q_out, *p_out;
+  const float *dt, *zeta, *h;
+  int32_t t, ld, n_pad, r_pad;
+  float k, inv_m, qmax, pmax;
+  int32_t order, wall;
+};
+hipError_t launch_step_bf16(int32_t tile, int32_t precision, const BStepArgs &a, hipStream_t s);
+hipError_t launch_pack_j_lowp(const float *J, int64_t total, int32_t precision, void *out_a,
+                              void *out_b, hipStream_t s);
+hipError_t launch_split_planes(const float *q, uint16_t *planes, int64_t total, int32_t nplanes,
+                               hipStream_t s);
 
 // G = J.sign(Q) in FP32, per-row-tile partial sums of s_i (G_i + 2 h_i):
 // part[row_tile][r].  BM is fixed at 64 rows.

@@ -75,6 +75,9 @@ struct si_ctx {
   int32_t tile = 0;
   float *J = nullptr;
   int8_t *J8 = nullptr;
+  void *Ja = nullptr, *Jb = nullptr;        // low-precision J planes
+  uint16_t *qb[2] = {nullptr, nullptr};     // BF16 plane(s) of q, ping-pong
+  int32_t qplanes = 0;                      // 0 for the FP32 form
   float *q[2] = {nullptr, nullptr}, *p[2] = {nullptr, nullptr};
   int cur = 0;
   float *dt = nullptr, *zeta = nullptr;
@@ -144,17 +147,41 @@ static si_status check_params(const si_params *p) {
     return fail(SI_ERR_INVALID, "params: unknown wall %d", p->wall);
   if (p->precision < SI_PREC_FP32 || p->precision > SI_PREC_BF16X3_EXACTJ)
     return fail(SI_ERR_INVALID, "params: unknown precision %d", p->precision);
-  if (p->tile < 0 || p->tile > TILE_F32_LAST)
+  const int32_t last = p->precision == SI_PREC_FP32 ? TILE_F32_LAST : TILE_BF16_LAST;
+  if (p->tile < 0 || p->tile > last)
     return fail(SI_ERR_INVALID, "params: unknown tile %d", p->tile);
   return SI_OK;
 }
 
 // Largest-work tile that still gives at least one workgroup per CU; with no
 // such tile, the one with the most workgroups (small problems).
+static TileShape shape_of(int32_t precision, int32_t tile) {
+  return precision == SI_PREC_FP32 ? tile_shape(tile) : tile_shape_bf16(tile);
+}
+
+static int32_t choose_tile_bf16(int32_t n, int32_t r, int num_cus) {
+  const int32_t order[] = {1, 2, 3, 4};
+  int32_t best = 1;
+  int64_t best_tiles = -1;
+  for (int32_t t : order) {
+    TileShape ts = tile_shape_bf16(t);
+    const int64_t np = round_up(n, ts.bm > 64 ? ts.bm : 64);
+    const int64_t rp = round_up(r, ts.bn > 64 ? ts.bn : 64);
+    const int64_t tiles = (np / ts.bm) * (rp / ts.bn);
+    if (tiles >= num_cus) return t;
+    if (tiles > best_tiles) {
+      best_tiles = tiles;
+      best = t;
+    }
+  }
+  return best;
+}
+
 static int32_t choose_tile(int32_t n, int32_t r, int num_cus) {
-  const int32_t order[] = {TILE_F32_64x128, TILE_F32_128x64, TILE_F32_64x64, TILE_F32_32x64,
-                           TILE_F32_32x32};
-  int32_t best = TILE_F32_32x32;
+  // Preference from a tile sweep at N=2000, R=1024 on MI355X: 64x64 tiles
+  // (two workgroups per CU) with the 32x32x2 MFMA and 64-deep slabs lead.
+  const int32_t order[] = {9, 2, 12, 6, 3};
+  int32_t best = 3;
   int64_t best_tiles = -1;
   for (int32_t t : order) {
     TileShape ts = tile_shape(t);
@@ -204,9 +231,6 @@ si_status spring_ising_init(si_ctx **out, int32_t n, int32_t r, const float *J, 
   if (!J || !x0) return fail(SI_ERR_INVALID, "init: J and x0 are required");
   si_status st = check_params(prm);
   if (st != SI_OK) return st;
-  if (prm->precision != SI_PREC_FP32)
-    return fail(SI_ERR_UNSUPPORTED, "init: precision %d is not available in this build",
-                prm->precision);
   if (!is_device_ptr(J) || !is_device_ptr(x0) || (p0 && !is_device_ptr(p0)))
     return fail(SI_ERR_INVALID, "init: J, x0 and p0 must be device pointers");
 
@@ -228,9 +252,11 @@ si_status spring_ising_init(si_ctx **out, int32_t n, int32_t r, const float *J, 
   INIT_HIP(hipGetDevice(&c->device));
   INIT_HIP(hipDeviceGetAttribute(&c->num_cus, hipDeviceAttributeMultiprocessorCount, c->device));
 
-  c->tile = prm->tile ? prm->tile : choose_tile(n, r, c->num_cus);
-  const TileShape ts = tile_shape(c->tile);
-  c->n_pad = (int32_t)round_up(n, ts.bm > 64 ? ts.bm : 64);
+  const bool lowp = prm->precision != SI_PREC_FP32;
+  c->tile = prm->tile ? prm->tile
+                      : (lowp ? choose_tile_bf16(n, r, c->num_cus) : choose_tile(n, r, c->num_cus));
+  const TileShape ts = shape_of(prm->precision, c->tile);
+  c->n_pad = (int32_t)round_up(n, ts.bm > 128 ? ts.bm : 128);
   c->r_pad = (int32_t)round_up(r, ts.bn > 64 ? ts.bn : 64);
 
   // validation of J: one host round trip
@@ -247,6 +273,13 @@ si_status spring_ising_init(si_ctx **out, int32_t n, int32_t r, const float *J, 
                 "(asymmetric=%d nonzero_diagonal=%d nonfinite=%d)", a, d, f);
   }
   const bool j_integer = c->hflags[3] == 0;
+  const bool need_bf16 = prm->precision == SI_PREC_BF16X_BF16J ||
+                         prm->precision == SI_PREC_BF16X3_EXACTJ;
+  if ((need_bf16 && c->hflags[5]) || (prm->precision == SI_PREC_BF16X_FP8J && c->hflags[4])) {
+    delete c;
+    return fail(SI_ERR_UNSUPPORTED, "init: precision %d needs J exact in %s", prm->precision,
+                need_bf16 ? "BF16" : "FP8 e4m3");
+  }
 
   const int64_t nn = (int64_t)c->n_pad * c->n_pad;
   const int64_t nr = (int64_t)c->n_pad * c->r_pad;
@@ -262,9 +295,19 @@ si_status spring_ising_init(si_ctx **out, int32_t n, int32_t r, const float *J, 
   INIT_HIP(c->alloc(&c->eacc, c->r_pad));
   INIT_HIP(c->alloc(&c->epart, (int64_t)(c->n_pad / 64) * c->r_pad));
 
+  if (lowp) {
+    c->qplanes = prm->precision == SI_PREC_BF16X3_EXACTJ ? 3 : 1;
+    const int64_t jbytes = prm->precision == SI_PREC_BF16X_FP8J ? 1 : 2;
+    INIT_HIP(c->alloc(reinterpret_cast<uint8_t **>(&c->Ja), nn * jbytes));
+    if (prm->precision == SI_PREC_BF16X_HILOJ)
+      INIT_HIP(c->alloc(reinterpret_cast<uint16_t **>(&c->Jb), nn));
+    for (int b = 0; b < 2; ++b) INIT_HIP(c->alloc(&c->qb[b], nr * c->qplanes));
+  }
   INIT_HIP(launch_pack_matrix(J, n, c->J, c->J8, c->n_pad, c->stream));
+  if (lowp) INIT_HIP(launch_pack_j_lowp(c->J, nn, prm->precision, c->Ja, c->Jb, c->stream));
   INIT_HIP(launch_pack_state(x0, n, r, c->q[0], c->n_pad, c->r_pad, c->stream));
   INIT_HIP(launch_pack_state(p0, n, r, c->p[0], c->n_pad, c->r_pad, c->stream));
+  if (lowp) INIT_HIP(launch_split_planes(c->q[0], c->qb[0], nr, c->qplanes, c->stream));
   INIT_HIP(launch_zero_i32(c->eacc, c->r_pad, c->stream));
   build_schedules(*prm, c->host_dt, c->host_zeta);
   INIT_HIP(hipMemcpyAsync(c->dt, c->host_dt.data(), sizeof(float) * prm->total_steps,
@@ -322,7 +365,40 @@ si_status spring_ising_set_field(si_ctx *c, const float *h) {
   return SI_OK;
 }
 
+static si_status do_steps_lowp(si_ctx *c, int32_t n_steps) {
+  BStepArgs a;
+  a.Ja = c->Ja;
+  a.Jb = c->Jb;
+  a.plane_stride = (int64_t)c->n_pad * c->r_pad;
+  a.dt = c->dt;
+  a.zeta = c->zeta;
+  a.h = c->has_field ? c->hf : nullptr;
+  a.ld = c->n_pad;
+  a.n_pad = c->n_pad;
+  a.r_pad = c->r_pad;
+  a.k = c->prm.k;
+  a.inv_m = 1.0f / c->prm.m;
+  a.qmax = c->prm.qmax;
+  a.pmax = c->prm.pmax;
+  a.order = c->prm.order;
+  a.wall = c->prm.wall;
+  for (int32_t s = 0; s < n_steps; ++s) {
+    a.q_in = c->q[c->cur];
+    a.p_in = c->p[c->cur];
+    a.q_out = c->q[c->cur ^ 1];
+    a.p_out = c->p[c->cur ^ 1];
+    a.qb_in = c->qb[c->cur];
+    a.qb_out = c->qb[c->cur ^ 1];
+    a.t = c->t;
+    SI_HIP(c, launch_step_bf16(c->tile, c->prm.precision, a, c->stream));
+    c->cur ^= 1;
+    c->t += 1;
+  }
+  return SI_OK;
+}
+
 static si_status do_steps(si_ctx *c, int32_t n_steps) {
+  if (c->qplanes) return do_steps_lowp(c, n_steps);
   StepArgs a;
   a.J = c->J;
   a.dt = c->dt;
@@ -421,6 +497,9 @@ si_status spring_ising_set_state(si_ctx *c, const float *x, const float *p, int3
     return fail(SI_ERR_RANGE, "set_state: t=%d outside [0, %d]", t, c->prm.total_steps);
   SI_HIP(c, launch_pack_state(x, c->n, c->r, c->q[c->cur], c->n_pad, c->r_pad, c->stream));
   SI_HIP(c, launch_pack_state(p, c->n, c->r, c->p[c->cur], c->n_pad, c->r_pad, c->stream));
+  if (c->qplanes)
+    SI_HIP(c, launch_split_planes(c->q[c->cur], c->qb[c->cur], (int64_t)c->n_pad * c->r_pad,
+                                  c->qplanes, c->stream));
   c->t = t;
   return SI_OK;
 }
@@ -441,7 +520,8 @@ si_status spring_ising_info(si_ctx *c, si_info *info) {
   info->precision = c->prm.precision;
   info->graph_steps = 0;
   info->device_bytes = c->bytes;
-  snprintf(info->kernel_name, sizeof info->kernel_name, "%s", tile_shape(c->tile).name);
+  snprintf(info->kernel_name, sizeof info->kernel_name, "%s",
+           shape_of(c->prm.precision, c->tile).name);
   return SI_OK;
 }
 

@@ -1,0 +1,377 @@
+// BF16 matrix-core forms of the coupling product fused with the update.
+//
+// Same iteration as the FP32 kernel (Eq. 8 with the walls and the zeta_n /
+// Delta_n weights, master q and p in FP32), but the product F = J.Q runs on
+// v_mfma_f32_32x32x16_bf16 with FP32 accumulation.  Operand formats:
+//   J planes: one BF16 plane (J exact in BF16, e.g. +-1), one FP8 e4m3 plane
+//     (J exact in FP8; expanded to BF16 while staged into LDS, so HBM and L2
+//     carry one byte per coupling), or two BF16 planes hi = bf16(J) and
+//     lo = bf16(J - hi) for real-valued J.
+//   Q planes: one BF16 copy of the FP32 master positions, or three BF16
+//     planes hi + mid + lo whose sum is the FP32 value exactly; with J exact
+//     in BF16 every product is then exact and only the FP32 accumulation
+//     rounds.
+// The epilogue writes the new FP32 master state and the BF16 plane(s) of q
+// that the next step consumes.
+//
+// MFMA layout (32x32x16, one block): lane l supplies 8 consecutive
+// contraction slots of row l%32 of A and of column l%32 of B, slot group
+// l/32; the result D[8(v/4)+4(l/32)+v%4][l%32] lands in accumulator v.
+// Each lane fills its 8 slots with 8 contiguous contraction indices read by
+// one 128-bit LDS load, identically for A and B, so the product sums every
+// index exactly once.
+#include "si_internal.h"
+
+namespace si {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned int uintx4 __attribute__((ext_vector_type(4)));
+typedef unsigned int uintx2 __attribute__((ext_vector_type(2)));
+
+// FP32 -> BF16 bits, round to nearest even (inputs are finite).
+__device__ __forceinline__ uint32_t bf16_bits(float x) {
+  uint32_t u = __float_as_uint(x);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return u >> 16;
+}
+__device__ __forceinline__ float bf16_to_f32(uint32_t b) { return __uint_as_float(b << 16); }
+
+// FP8 e4m3 (bias 7, no infinities) -> BF16 bits; exact because every e4m3
+// value has at most 4 significant bits.
+__device__ __forceinline__ uint32_t fp8_to_bf16_bits(uint32_t b) {
+  const uint32_t sign = (b & 0x80u) << 8;
+  const uint32_t e = (b >> 3) & 0xFu, m = b & 7u;
+  if (e == 0) {
+    if (m == 0) return sign;
+    // subnormal: m * 2^-9
+    const float v = (float)m * 0.001953125f;
+    return sign | (__float_as_uint(v) >> 16);
+  }
+  // normal: (1 + m/8) * 2^(e-7): bf16 exponent e - 7 + 127, mantissa m << 4
+  return sign | ((e + 120u) << 7) | (m << 4);
+}
+
+template <int BM_, int BN_, int WM_, int WN_, int BK_, int JFMT_, int QP_>
+struct Bf16Cfg {
+  static constexpr int BM = BM_, BN = BN_, WM = WM_, WN = WN_, BK = BK_;
+  static constexpr int JFMT = JFMT_;  // 0: bf16 J, 1: fp8 J, 2: hi/lo bf16 J
+  static constexpr int QP = QP_;      // BF16 planes of Q: 1 or 3
+  static constexpr int JP = JFMT == 2 ? 2 : 1;
+  static constexpr int MB = 32, KSTEP = 16;
+  static constexpr int LDK = BK + 8;  // bf16 elements per padded LDS row (144 B for BK=64)
+  static constexpr int WTM = BM / WM, WTN = BN / WN;
+  static constexpr int TM = WTM / MB, TN = WTN / MB;
+  static constexpr int NT = 64 * WM * WN;
+  static constexpr int V8_PER_ROW = BK / 8;        // 16-byte vectors per row of a slab
+  static constexpr int ROWS_PER_PASS = NT / V8_PER_ROW;
+  static constexpr int A_V = BM * BK / 8 / NT;     // vectors per thread per plane
+  static constexpr int B_V = BN * BK / 8 / NT;
+  static_assert(TM >= 1 && TN >= 1 && WTM % MB == 0 && WTN % MB == 0, "wave tile");
+  static_assert(A_V >= 1 && B_V >= 1 && (BM * BK / 8) % NT == 0 && (BN * BK / 8) % NT == 0,
+                "slab loads");
+  static constexpr int A_ELEMS = BM * LDK, B_ELEMS = BN * LDK;
+  static constexpr int STAGE_ELEMS = JP * A_ELEMS + QP * B_ELEMS;
+  static constexpr int LDS_ELEMS = 2 * STAGE_ELEMS;
+};
+
+template <class C>
+__device__ __forceinline__ void bf16_mainloop(const BStepArgs &a, int m0, int n0,
+                                              floatx16 (&acc)[C::TM][C::TN], uint16_t *smem) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wy = wave / C::WN, wx = wave % C::WN;
+  const int lrow = lane % 32, lk = (lane / 32) * 8;
+  const int ld = a.ld;
+#pragma unroll
+  for (int i = 0; i < C::TM; ++i)
+#pragma unroll
+    for (int j = 0; j < C::TN; ++j)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.f;
+
+  const int srow = tid / C::V8_PER_ROW, sc8 = (tid % C::V8_PER_ROW) * 8;
+  uintx4 ra[C::JP][C::A_V], rb[C::QP][C::B_V];
+  uintx2 ra8[C::A_V];
+
+  auto gload = [&](int k0) {
+    if (C::JFMT == 1) {
+      const uint8_t *g = reinterpret_cast<const uint8_t *>(a.Ja) + (size_t)(m0 + srow) * ld + sc8 + k0;
+#pragma unroll
+      for (int f = 0; f < C::A_V; ++f)
+        ra8[f] = *reinterpret_cast<const uintx2 *>(g + (size_t)f * C::ROWS_PER_PASS * ld);
+    } else {
+#pragma unroll
+      for (int pl = 0; pl < C::JP; ++pl) {
+        const uint16_t *g = (pl == 0 ? reinterpret_cast<const uint16_t *>(a.Ja)
+                                     : reinterpret_cast<const uint16_t *>(a.Jb)) +
+                            (size_t)(m0 + srow) * ld + sc8 + k0;
+#pragma unroll
+        for (int f = 0; f < C::A_V; ++f)
+          ra[pl][f] = *reinterpret_cast<const uintx4 *>(g + (size_t)f * C::ROWS_PER_PASS * ld);
+      }
+    }
+#pragma unroll
+    for (int pl = 0; pl < C::QP; ++pl) {
+      const uint16_t *g = a.qb_in + (size_t)pl * a.plane_stride + (size_t)(n0 + srow) * ld + sc8 + k0;
+#pragma unroll
+      for (int f = 0; f < C::B_V; ++f)
+        rb[pl][f] = *reinterpret_cast<const uintx4 *>(g + (size_t)f * C::ROWS_PER_PASS * ld);
+    }
+  };
+  auto sstore = [&](int buf) {
+    uint16_t *st = smem + buf * C::STAGE_ELEMS;
+#pragma unroll
+    for (int f = 0; f < C::A_V; ++f) {
+      const int off = (srow + f * C::ROWS_PER_PASS) * C::LDK + sc8;
+      if (C::JFMT == 1) {
+        uintx4 w;
+        const uint32_t lo = ra8[f][0], hi = ra8[f][1];
+        w[0] = fp8_to_bf16_bits(lo & 0xFF) | (fp8_to_bf16_bits((lo >> 8) & 0xFF) << 16);
+        w[1] = fp8_to_bf16_bits((lo >> 16) & 0xFF) | (fp8_to_bf16_bits(lo >> 24) << 16);
+        w[2] = fp8_to_bf16_bits(hi & 0xFF) | (fp8_to_bf16_bits((hi >> 8) & 0xFF) << 16);
+        w[3] = fp8_to_bf16_bits((hi >> 16) & 0xFF) | (fp8_to_bf16_bits(hi >> 24) << 16);
+        *reinterpret_cast<uintx4 *>(st + off) = w;
+      } else {
+#pragma unroll
+        for (int pl = 0; pl < C::JP; ++pl)
+          *reinterpret_cast<uintx4 *>(st + pl * C::A_ELEMS + off) = ra[pl][f];
+      }
+    }
+#pragma unroll
+    for (int pl = 0; pl < C::QP; ++pl)
+#pragma unroll
+      for (int f = 0; f < C::B_V; ++f)
+        *reinterpret_cast<uintx4 *>(st + C::JP * C::A_ELEMS + pl * C::B_ELEMS +
+                                    (srow + f * C::ROWS_PER_PASS) * C::LDK + sc8) = rb[pl][f];
+  };
+
+  const int nk = a.n_pad / C::BK;
+  gload(0);
+  sstore(0);
+  __syncthreads();
+  for (int kt = 0; kt < nk; ++kt) {
+    const int buf = kt & 1;
+    if (kt + 1 < nk) gload((kt + 1) * C::BK);
+    const uint16_t *st = smem + buf * C::STAGE_ELEMS;
+    const uint16_t *as = st + (wy * C::WTM + lrow) * C::LDK + lk;
+    const uint16_t *bs = st + C::JP * C::A_ELEMS + (wx * C::WTN + lrow) * C::LDK + lk;
+#pragma unroll
+    for (int kk = 0; kk < C::BK; kk += C::KSTEP) {
+      bf16x8 fa[C::JP][C::TM], fb[C::QP][C::TN];
+#pragma unroll
+      for (int pl = 0; pl < C::JP; ++pl)
+#pragma unroll
+        for (int i = 0; i < C::TM; ++i)
+          fa[pl][i] = *reinterpret_cast<const bf16x8 *>(as + pl * C::A_ELEMS + i * 32 * C::LDK + kk);
+#pragma unroll
+      for (int pl = 0; pl < C::QP; ++pl)
+#pragma unroll
+        for (int j = 0; j < C::TN; ++j)
+          fb[pl][j] = *reinterpret_cast<const bf16x8 *>(bs + pl * C::B_ELEMS + j * 32 * C::LDK + kk);
+#pragma unroll
+      for (int i = 0; i < C::TM; ++i)
+#pragma unroll
+        for (int j = 0; j < C::TN; ++j) {
+#pragma unroll
+          for (int pa = 0; pa < C::JP; ++pa)
+#pragma unroll
+            for (int pb = 0; pb < C::QP; ++pb)
+              acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[pa][i], fb[pb][j], acc[i][j],
+                                                                  0, 0, 0);
+        }
+    }
+    if (kt + 1 < nk) sstore(buf ^ 1);
+    __syncthreads();
+  }
+}
+
+template <int ORDER, int WALL>
+__device__ __forceinline__ void update_b(float q, float p, float f, float dt, float zeta, float k,
+                                         float inv_m, float qmax, float pmax, float &qn,
+                                         float &pn) {
+  const float c = dt * inv_m;
+  const float force = fmaf(zeta, f, -k * q);
+  const float v = fmaf(dt, force, p);
+  pn = fminf(fmaxf(v, -pmax), pmax);
+  const float u = ORDER == SI_ORDER_PAPER ? fmaf(c, p, q) : fmaf(c, pn, q);
+  qn = fminf(fmaxf(u, -qmax), qmax);
+  if (WALL == SI_WALL_INELASTIC && fabsf(u) > qmax) pn = 0.f;
+}
+
+template <class C, int ORDER, int WALL>
+__global__ __launch_bounds__(C::NT) void step_bf16_kernel(BStepArgs a) {
+  __shared__ __attribute__((aligned(16))) uint16_t smem[C::LDS_ELEMS];
+  const int m0 = blockIdx.x * C::BM, n0 = blockIdx.y * C::BN;
+  floatx16 acc[C::TM][C::TN];
+  bf16_mainloop<C>(a, m0, n0, acc, smem);
+
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wy = wave / C::WN, wx = wave % C::WN;
+  const float dt = a.dt[a.t], zeta = a.zeta[a.t];
+#pragma unroll
+  for (int i = 0; i < C::TM; ++i)
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      const int row = m0 + wy * C::WTM + i * 32 + g * 8 + (lane / 32) * 4;
+      floatx4 h4 = {0.f, 0.f, 0.f, 0.f};
+      if (a.h) h4 = *reinterpret_cast<const floatx4 *>(a.h + row);
+#pragma unroll
+      for (int j = 0; j < C::TN; ++j) {
+        const int col = n0 + wx * C::WTN + j * 32 + (lane % 32);
+        const size_t off = (size_t)col * a.ld + row;
+        const floatx4 q4 = *reinterpret_cast<const floatx4 *>(a.q_in + off);
+        const floatx4 p4 = *reinterpret_cast<const floatx4 *>(a.p_in + off);
+        floatx4 qn, pn;
+        uint32_t b0[4], b1[4], b2[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          float qv, pv;
+          update_b<ORDER, WALL>(q4[v], p4[v], acc[i][j][4 * g + v] + h4[v], dt, zeta, a.k,
+                                a.inv_m, a.qmax, a.pmax, qv, pv);
+          qn[v] = qv;
+          pn[v] = pv;
+          b0[v] = bf16_bits(qv);
+          if (C::QP == 3) {
+            const float r1 = qv - bf16_to_f32(b0[v]);  // exact
+            b1[v] = bf16_bits(r1);
+            const float r2 = r1 - bf16_to_f32(b1[v]);  // exact
+            b2[v] = bf16_bits(r2);
+          }
+        }
+        *reinterpret_cast<floatx4 *>(a.q_out + off) = qn;
+        *reinterpret_cast<floatx4 *>(a.p_out + off) = pn;
+        uint16_t *qb = a.qb_out + off;
+        *reinterpret_cast<uintx2 *>(qb) = uintx2{b0[0] | (b0[1] << 16), b0[2] | (b0[3] << 16)};
+        if (C::QP == 3) {
+          *reinterpret_cast<uintx2 *>(qb + a.plane_stride) =
+              uintx2{b1[0] | (b1[1] << 16), b1[2] | (b1[3] << 16)};
+          *reinterpret_cast<uintx2 *>(qb + 2 * a.plane_stride) =
+              uintx2{b2[0] | (b2[1] << 16), b2[2] | (b2[3] << 16)};
+        }
+      }
+    }
+}
+
+// BF16 tile table: id, BM, BN, waves WM x WN, slab depth BK.
+#define SI_BF16_TILES(X)      \
+  X(1, 64, 64, 2, 2, 64)      \
+  X(2, 64, 128, 2, 2, 64)     \
+  X(3, 128, 64, 2, 2, 64)     \
+  X(4, 128, 128, 2, 2, 64)    \
+  X(5, 128, 128, 2, 4, 64)    \
+  X(6, 64, 64, 2, 2, 128)
+
+TileShape tile_shape_bf16(int32_t tile) {
+  switch (tile) {
+#define SI_SHAPE(id, bm, bn, wm, wn, bk) \
+  case id:                               \
+    return {bm, bn, "step_bf16_" #bm "x" #bn "_w" #wm "x" #wn "_k" #bk};
+    SI_BF16_TILES(SI_SHAPE)
+#undef SI_SHAPE
+    default: return {0, 0, "invalid"};
+  }
+}
+
+template <class C>
+static hipError_t launch_b(const BStepArgs &a, hipStream_t s) {
+  if (a.n_pad % C::BM || a.r_pad % C::BN || a.n_pad % C::BK) return hipErrorInvalidValue;
+  dim3 grid(a.n_pad / C::BM, a.r_pad / C::BN), block(C::NT);
+  switch (a.order * 2 + a.wall) {
+    case 0: step_bf16_kernel<C, SI_ORDER_PAPER, SI_WALL_CLAMP><<<grid, block, 0, s>>>(a); break;
+    case 1: step_bf16_kernel<C, SI_ORDER_PAPER, SI_WALL_INELASTIC><<<grid, block, 0, s>>>(a); break;
+    case 2: step_bf16_kernel<C, SI_ORDER_SYMPLECTIC, SI_WALL_CLAMP><<<grid, block, 0, s>>>(a); break;
+    case 3: step_bf16_kernel<C, SI_ORDER_SYMPLECTIC, SI_WALL_INELASTIC><<<grid, block, 0, s>>>(a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <int JFMT, int QP>
+static hipError_t launch_fmt(int32_t tile, const BStepArgs &a, hipStream_t s) {
+  switch (tile) {
+#define SI_LAUNCH(id, bm, bn, wm, wn, bk) \
+  case id:                                \
+    return launch_b<Bf16Cfg<bm, bn, wm, wn, bk, JFMT, QP>>(a, s);
+    SI_BF16_TILES(SI_LAUNCH)
+#undef SI_LAUNCH
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_step_bf16(int32_t tile, int32_t precision, const BStepArgs &a, hipStream_t s) {
+  switch (precision) {
+    case SI_PREC_BF16X_BF16J: return launch_fmt<0, 1>(tile, a, s);
+    case SI_PREC_BF16X_FP8J: return launch_fmt<1, 1>(tile, a, s);
+    case SI_PREC_BF16X_HILOJ: return launch_fmt<2, 1>(tile, a, s);
+    case SI_PREC_BF16X3_EXACTJ: return launch_fmt<0, 3>(tile, a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Packing for the precision forms.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t f32_to_fp8_exact(float v) {
+  // v is known to be exact in e4m3 (validated); encode it.
+  uint32_t sign = v < 0.f ? 0x80u : 0u;
+  const float a = fabsf(v);
+  if (a == 0.f) return sign;
+  if (a < 0.015625f) return sign | (uint32_t)(a * 512.f);  // subnormal, exponent field 0
+  int e;
+  const float fr = frexpf(a, &e);  // a = fr * 2^e, fr in [0.5, 1)
+  const uint32_t exp_field = (uint32_t)(e - 1 + 7);
+  const uint32_t man = (uint32_t)(fr * 16.f) - 8u;
+  return sign | (exp_field << 3) | man;
+}
+
+__global__ void pack_j_lowp_kernel(const float *__restrict__ J, int64_t total, int fmt,
+                                   void *__restrict__ out_a, void *__restrict__ out_b) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const float v = J[i];
+    if (fmt == 1) {
+      reinterpret_cast<uint8_t *>(out_a)[i] = (uint8_t)f32_to_fp8_exact(v);
+    } else {
+      const uint32_t hi = bf16_bits(v);
+      reinterpret_cast<uint16_t *>(out_a)[i] = (uint16_t)hi;
+      if (fmt == 2) reinterpret_cast<uint16_t *>(out_b)[i] = (uint16_t)bf16_bits(v - bf16_to_f32(hi));
+    }
+  }
+}
+
+__global__ void split_planes_kernel(const float *__restrict__ q, uint16_t *__restrict__ planes,
+                                    int64_t total, int nplanes) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    float r = q[i];
+    for (int pl = 0; pl < nplanes; ++pl) {
+      const uint32_t b = bf16_bits(r);
+      planes[(size_t)pl * total + i] = (uint16_t)b;
+      r = r - bf16_to_f32(b);
+    }
+  }
+}
+
+static int grid_for(int64_t total) {
+  int64_t b = (total + 255) / 256;
+  if (b > 8192) b = 8192;
+  return b < 1 ? 1 : (int)b;
+}
+
+hipError_t launch_pack_j_lowp(const float *J, int64_t total, int32_t precision, void *out_a,
+                              void *out_b, hipStream_t s) {
+  int fmt = 0;
+  if (precision == SI_PREC_BF16X_FP8J) fmt = 1;
+  if (precision == SI_PREC_BF16X_HILOJ) fmt = 2;
+  pack_j_lowp_kernel<<<grid_for(total), 256, 0, s>>>(J, total, fmt, out_a, out_b);
+  return hipGetLastError();
+}
+
+hipError_t launch_split_planes(const float *q, uint16_t *planes, int64_t total, int32_t nplanes,
+                               hipStream_t s) {
+  split_planes_kernel<<<grid_for(total), 256, 0, s>>>(q, planes, total, nplanes);
+  return hipGetLastError();
+}
+
+}  // namespace si

@@ -9,34 +9,62 @@
 // Layout: J is [n_pad][n_pad] (symmetric, so row i of J is also column i),
 // Q and P are [r_pad][n_pad] (replica-major).  Both GEMM operands are
 // therefore contiguous along the contraction index: the tile loop stages a
-// BM x 32 slab of J and a BN x 32 slab of Q through LDS per iteration and
+// BM x BK slab of J and a BN x BK slab of Q through LDS per iteration and
 // the waves read them with 128-bit LDS loads.
 //
-// MFMA used: v_mfma_f32_16x16x4_f32.  For one 16x16 block, lane l supplies
-// A[l%16][l/16] and B[l/16][l%16]; the result D[4*(l/16)+v][l%16] lands in
-// accumulator element v.  Four consecutive MFMAs consume 16 contraction
-// indices; lane group g = l/16 owns indices kk+4g .. kk+4g+3 (one 128-bit
-// LDS read per operand), MFMA s using the s-th of them.  Every index is
-// summed exactly once, so this is only a permutation of the contraction.
+// Two MFMA shapes are used (MB = block edge):
+//   MB = 16: v_mfma_f32_16x16x4_f32.  Lane l supplies A[l%16][l/16] and
+//            B[l/16][l%16]; result D[4(l/16)+v][l%16] in accumulator v < 4.
+//   MB = 32: v_mfma_f32_32x32x2_f32.  Lane l supplies A[l%32][l/32] and
+//            B[l/32][l%32]; result D[8(v/4)+4(l/32)+v%4][l%32], v < 16.
+// In both, lane group g = l/MB reads the four contraction indices
+// kk+4g .. kk+4g+3 with one 128-bit LDS load per operand and MFMA s uses the
+// s-th of them; each index is summed exactly once, in increasing kk order,
+// so the permutation only changes which lane holds which index.
 #include "si_internal.h"
 
 namespace si {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef float floatx16 __attribute__((ext_vector_type(16)));
 
-template <int BM_, int BN_, int WM_, int WN_>
+template <int MB>
+struct MfmaF32;
+template <>
+struct MfmaF32<16> {
+  using acc_t = floatx4;
+  static constexpr int NACC = 4;
+  static __device__ __forceinline__ acc_t mma(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+};
+template <>
+struct MfmaF32<32> {
+  using acc_t = floatx16;
+  static constexpr int NACC = 16;
+  static __device__ __forceinline__ acc_t mma(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
+  }
+};
+
+template <int BM_, int BN_, int WM_, int WN_, int MB_, int BK_>
 struct F32Cfg {
-  static constexpr int BM = BM_, BN = BN_, WM = WM_, WN = WN_;
-  static constexpr int BK = 32;
+  static constexpr int BM = BM_, BN = BN_, WM = WM_, WN = WN_, MB = MB_, BK = BK_;
   static constexpr int LDK = BK + 4;  // padded LDS row: conflict-free 128-bit reads
   static constexpr int WTM = BM / WM, WTN = BN / WN;
-  static constexpr int TM = WTM / 16, TN = WTN / 16;
-  static constexpr int NT = 256;
+  static constexpr int TM = WTM / MB, TN = WTN / MB;
+  static constexpr int NT = 64 * WM * WN;
+  static constexpr int KSTEP = 64 / MB * 4;  // contraction indices per LDS read step
+  static constexpr int F4_PER_ROW = BK / 4;
+  static constexpr int ROWS_PER_PASS = NT / F4_PER_ROW;
   static constexpr int A_F4 = BM * BK / 4 / NT;  // float4 loads per thread
   static constexpr int B_F4 = BN * BK / 4 / NT;
-  static_assert(WM * WN == 4, "four waves per workgroup");
-  static_assert(TM >= 1 && TN >= 1 && WTM % 16 == 0 && WTN % 16 == 0, "wave tile");
-  static_assert(A_F4 >= 1 && B_F4 >= 1, "slab loads");
+  using M = MfmaF32<MB>;
+  using acc_t = typename M::acc_t;
+  static_assert(TM >= 1 && TN >= 1 && WTM % MB == 0 && WTN % MB == 0, "wave tile");
+  static_assert(A_F4 >= 1 && B_F4 >= 1 && BM * BK / 4 % NT == 0 && BN * BK / 4 % NT == 0,
+                "slab loads");
+  static_assert(BK % KSTEP == 0, "slab depth");
   static constexpr int LDS_FLOATS = 2 * (BM + BN) * LDK;
 };
 
@@ -47,7 +75,8 @@ __device__ __forceinline__ float sign_pm1(float x) { return x < 0.f ? -1.f : 1.f
 template <class C, bool SIGN_B>
 __device__ __forceinline__ void f32_mainloop(const float *__restrict__ A,
                                              const float *__restrict__ B, int ld, int K,
-                                             int m0, int n0, floatx4 (&acc)[C::TM][C::TN],
+                                             int m0, int n0,
+                                             typename C::acc_t (&acc)[C::TM][C::TN],
                                              float *smem) {
   float *As = smem;                          // [2][BM][LDK]
   float *Bs = smem + 2 * C::BM * C::LDK;     // [2][BN][LDK]
@@ -55,37 +84,39 @@ __device__ __forceinline__ void f32_mainloop(const float *__restrict__ A,
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int wy = wave / C::WN, wx = wave % C::WN;
-  const int lrow = lane & 15, lk = (lane >> 4) * 4;
+  const int lrow = lane % C::MB, lk = (lane / C::MB) * 4;
 
 #pragma unroll
   for (int i = 0; i < C::TM; ++i)
 #pragma unroll
-    for (int j = 0; j < C::TN; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int j = 0; j < C::TN; ++j)
+#pragma unroll
+      for (int v = 0; v < C::M::NACC; ++v) acc[i][j][v] = 0.f;
 
   floatx4 ra[C::A_F4], rb[C::B_F4];
-  const float *ga = A + (size_t)(m0 + (tid >> 3)) * ld + (tid & 7) * 4;
-  const float *gb = B + (size_t)(n0 + (tid >> 3)) * ld + (tid & 7) * 4;
-  constexpr int ROWS_PER_PASS = C::NT / 8;  // 32 rows of 32 floats per pass
-  float *as_st = As + (tid >> 3) * C::LDK + (tid & 7) * 4;
-  float *bs_st = Bs + (tid >> 3) * C::LDK + (tid & 7) * 4;
-#define SI_GLOAD(k0)                                                                    \
-  {                                                                                     \
-    _Pragma("unroll") for (int f = 0; f < C::A_F4; ++f) ra[f] =                         \
-        *reinterpret_cast<const floatx4 *>(ga + (size_t)f * ROWS_PER_PASS * ld + (k0)); \
-    _Pragma("unroll") for (int f = 0; f < C::B_F4; ++f) {                               \
-      floatx4 v = *reinterpret_cast<const floatx4 *>(gb + (size_t)f * ROWS_PER_PASS * ld + (k0)); \
-      if (SIGN_B) {                                                                     \
+  const int srow = tid / C::F4_PER_ROW, sc4 = (tid % C::F4_PER_ROW) * 4;
+  const float *ga = A + (size_t)(m0 + srow) * ld + sc4;
+  const float *gb = B + (size_t)(n0 + srow) * ld + sc4;
+  float *as_st = As + srow * C::LDK + sc4;
+  float *bs_st = Bs + srow * C::LDK + sc4;
+#define SI_GLOAD(k0)                                                                      \
+  {                                                                                       \
+    _Pragma("unroll") for (int f = 0; f < C::A_F4; ++f) ra[f] =                           \
+        *reinterpret_cast<const floatx4 *>(ga + (size_t)f * C::ROWS_PER_PASS * ld + (k0));\
+    _Pragma("unroll") for (int f = 0; f < C::B_F4; ++f) {                                 \
+      floatx4 v = *reinterpret_cast<const floatx4 *>(gb + (size_t)f * C::ROWS_PER_PASS * ld + (k0)); \
+      if (SIGN_B) {                                                                       \
         v[0] = sign_pm1(v[0]); v[1] = sign_pm1(v[1]); v[2] = sign_pm1(v[2]); v[3] = sign_pm1(v[3]); \
-      }                                                                                 \
-      rb[f] = v;                                                                        \
-    }                                                                                   \
+      }                                                                                   \
+      rb[f] = v;                                                                          \
+    }                                                                                     \
   }
-#define SI_SSTORE(buf)                                                                  \
-  {                                                                                     \
-    _Pragma("unroll") for (int f = 0; f < C::A_F4; ++f) *reinterpret_cast<floatx4 *>(   \
-        as_st + (buf) * C::BM * C::LDK + f * ROWS_PER_PASS * C::LDK) = ra[f];           \
-    _Pragma("unroll") for (int f = 0; f < C::B_F4; ++f) *reinterpret_cast<floatx4 *>(   \
-        bs_st + (buf) * C::BN * C::LDK + f * ROWS_PER_PASS * C::LDK) = rb[f];           \
+#define SI_SSTORE(buf)                                                                    \
+  {                                                                                       \
+    _Pragma("unroll") for (int f = 0; f < C::A_F4; ++f) *reinterpret_cast<floatx4 *>(     \
+        as_st + (buf) * C::BM * C::LDK + f * C::ROWS_PER_PASS * C::LDK) = ra[f];          \
+    _Pragma("unroll") for (int f = 0; f < C::B_F4; ++f) *reinterpret_cast<floatx4 *>(     \
+        bs_st + (buf) * C::BN * C::LDK + f * C::ROWS_PER_PASS * C::LDK) = rb[f];          \
   }
 
   const int nk = K / C::BK;
@@ -98,27 +129,32 @@ __device__ __forceinline__ void f32_mainloop(const float *__restrict__ A,
     const float *as = As + buf * C::BM * C::LDK + (wy * C::WTM + lrow) * C::LDK + lk;
     const float *bs = Bs + buf * C::BN * C::LDK + (wx * C::WTN + lrow) * C::LDK + lk;
 #pragma unroll
-    for (int kk = 0; kk < C::BK; kk += 16) {
+    for (int kk = 0; kk < C::BK; kk += C::KSTEP) {
       floatx4 a[C::TM], b[C::TN];
 #pragma unroll
       for (int i = 0; i < C::TM; ++i)
-        a[i] = *reinterpret_cast<const floatx4 *>(as + i * 16 * C::LDK + kk);
+        a[i] = *reinterpret_cast<const floatx4 *>(as + i * C::MB * C::LDK + kk);
 #pragma unroll
       for (int j = 0; j < C::TN; ++j)
-        b[j] = *reinterpret_cast<const floatx4 *>(bs + j * 16 * C::LDK + kk);
+        b[j] = *reinterpret_cast<const floatx4 *>(bs + j * C::MB * C::LDK + kk);
 #pragma unroll
       for (int s = 0; s < 4; ++s)
 #pragma unroll
         for (int i = 0; i < C::TM; ++i)
 #pragma unroll
-          for (int j = 0; j < C::TN; ++j)
-            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i][s], b[j][s], acc[i][j], 0, 0, 0);
+          for (int j = 0; j < C::TN; ++j) acc[i][j] = C::M::mma(a[i][s], b[j][s], acc[i][j]);
     }
     if (kt + 1 < nk) SI_SSTORE(buf ^ 1);
     __syncthreads();
   }
 #undef SI_GLOAD
 #undef SI_SSTORE
+}
+
+// Row (within the MB x MB block) of accumulator element v for this lane.
+template <int MB>
+__device__ __forceinline__ int acc_row(int lane, int v) {
+  return (v / 4) * 8 + (lane / MB) * 4 + (v % 4);
 }
 
 // Eq. (8) + walls for one element.  f is sum_j J_ij q_j (+ h_i).
@@ -141,11 +177,11 @@ __device__ __forceinline__ void update(float q, float p, float f, float dt, floa
 }
 
 template <class C, int ORDER, int WALL>
-__global__ __launch_bounds__(256) void step_f32_kernel(StepArgs a) {
+__global__ __launch_bounds__(C::NT) void step_f32_kernel(StepArgs a) {
   __shared__ __attribute__((aligned(16))) float smem[C::LDS_FLOATS];
   const int m0 = blockIdx.x * C::BM;
   const int n0 = blockIdx.y * C::BN;
-  floatx4 acc[C::TM][C::TN];
+  typename C::acc_t acc[C::TM][C::TN];
   f32_mainloop<C, false>(a.J, a.q_in, a.ld, a.n_pad, m0, n0, acc, smem);
 
   const int lane = threadIdx.x & 63;
@@ -154,34 +190,55 @@ __global__ __launch_bounds__(256) void step_f32_kernel(StepArgs a) {
   const float dt = a.dt[a.t], zeta = a.zeta[a.t];
 #pragma unroll
   for (int i = 0; i < C::TM; ++i) {
-    const int row = m0 + wy * C::WTM + i * 16 + (lane >> 4) * 4;
-    float4 h4 = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (a.h) h4 = *reinterpret_cast<const float4 *>(a.h + row);
 #pragma unroll
-    for (int j = 0; j < C::TN; ++j) {
-      const int col = n0 + wx * C::WTN + j * 16 + (lane & 15);
-      const size_t off = (size_t)col * a.ld + row;
-      const float4 q4 = *reinterpret_cast<const float4 *>(a.q_in + off);
-      const float4 p4 = *reinterpret_cast<const float4 *>(a.p_in + off);
-      float4 qn, pn;
-      update<ORDER, WALL>(q4.x, p4.x, acc[i][j][0] + h4.x, dt, zeta, a.k, a.inv_m, a.qmax, a.pmax, qn.x, pn.x);
-      update<ORDER, WALL>(q4.y, p4.y, acc[i][j][1] + h4.y, dt, zeta, a.k, a.inv_m, a.qmax, a.pmax, qn.y, pn.y);
-      update<ORDER, WALL>(q4.z, p4.z, acc[i][j][2] + h4.z, dt, zeta, a.k, a.inv_m, a.qmax, a.pmax, qn.z, pn.z);
-      update<ORDER, WALL>(q4.w, p4.w, acc[i][j][3] + h4.w, dt, zeta, a.k, a.inv_m, a.qmax, a.pmax, qn.w, pn.w);
-      *reinterpret_cast<float4 *>(a.q_out + off) = qn;
-      *reinterpret_cast<float4 *>(a.p_out + off) = pn;
+    for (int g = 0; g < C::M::NACC / 4; ++g) {
+      const int row = m0 + wy * C::WTM + i * C::MB + g * 8 + (lane / C::MB) * 4;
+      floatx4 h4 = {0.f, 0.f, 0.f, 0.f};
+      if (a.h) h4 = *reinterpret_cast<const floatx4 *>(a.h + row);
+#pragma unroll
+      for (int j = 0; j < C::TN; ++j) {
+        const int col = n0 + wx * C::WTN + j * C::MB + (lane % C::MB);
+        const size_t off = (size_t)col * a.ld + row;
+        const floatx4 q4 = *reinterpret_cast<const floatx4 *>(a.q_in + off);
+        const floatx4 p4 = *reinterpret_cast<const floatx4 *>(a.p_in + off);
+        floatx4 qn, pn;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          float qv, pv;
+          update<ORDER, WALL>(q4[v], p4[v], acc[i][j][4 * g + v] + h4[v], dt, zeta, a.k, a.inv_m,
+                              a.qmax, a.pmax, qv, pv);
+          qn[v] = qv;
+          pn[v] = pv;
+        }
+        *reinterpret_cast<floatx4 *>(a.q_out + off) = qn;
+        *reinterpret_cast<floatx4 *>(a.p_out + off) = pn;
+      }
     }
   }
 }
 
+// Tile table: id, BM, BN, waves (WM x WN), MFMA block edge, slab depth BK.
+#define SI_F32_TILES(X)             \
+  X(1, 64, 128, 2, 2, 32, 32)       \
+  X(2, 64, 64, 2, 2, 32, 32)        \
+  X(3, 32, 32, 2, 2, 16, 32)        \
+  X(4, 128, 64, 2, 2, 32, 32)       \
+  X(5, 128, 128, 2, 2, 32, 32)      \
+  X(6, 32, 64, 2, 2, 16, 32)        \
+  X(7, 64, 128, 2, 2, 32, 64)       \
+  X(8, 64, 128, 2, 4, 32, 32)       \
+  X(9, 64, 64, 2, 2, 32, 64)        \
+  X(10, 64, 128, 2, 2, 16, 32)      \
+  X(11, 128, 128, 2, 4, 32, 32)     \
+  X(12, 64, 64, 2, 2, 16, 32)
+
 TileShape tile_shape(int32_t tile) {
   switch (tile) {
-    case TILE_F32_64x128: return {64, 128, "step_f32_64x128"};
-    case TILE_F32_64x64: return {64, 64, "step_f32_64x64"};
-    case TILE_F32_32x32: return {32, 32, "step_f32_32x32"};
-    case TILE_F32_128x64: return {128, 64, "step_f32_128x64"};
-    case TILE_F32_128x128: return {128, 128, "step_f32_128x128"};
-    case TILE_F32_32x64: return {32, 64, "step_f32_32x64"};
+#define SI_SHAPE(id, bm, bn, wm, wn, mb, bk) \
+  case id:                                   \
+    return {bm, bn, "step_f32_" #bm "x" #bn "_w" #wm "x" #wn "_mfma" #mb "_k" #bk};
+    SI_F32_TILES(SI_SHAPE)
+#undef SI_SHAPE
     default: return {0, 0, "invalid"};
   }
 }
@@ -203,12 +260,11 @@ static hipError_t launch_cfg(const StepArgs &a, hipStream_t s) {
 
 hipError_t launch_step_f32(int32_t tile, const StepArgs &a, hipStream_t s) {
   switch (tile) {
-    case TILE_F32_64x128: return launch_cfg<F32Cfg<64, 128, 2, 2>>(a, s);
-    case TILE_F32_64x64: return launch_cfg<F32Cfg<64, 64, 2, 2>>(a, s);
-    case TILE_F32_32x32: return launch_cfg<F32Cfg<32, 32, 2, 2>>(a, s);
-    case TILE_F32_128x64: return launch_cfg<F32Cfg<128, 64, 2, 2>>(a, s);
-    case TILE_F32_128x128: return launch_cfg<F32Cfg<128, 128, 2, 2>>(a, s);
-    case TILE_F32_32x64: return launch_cfg<F32Cfg<32, 64, 2, 2>>(a, s);
+#define SI_LAUNCH(id, bm, bn, wm, wn, mb, bk) \
+  case id:                                    \
+    return launch_cfg<F32Cfg<bm, bn, wm, wn, mb, bk>>(a, s);
+    SI_F32_TILES(SI_LAUNCH)
+#undef SI_LAUNCH
     default: return hipErrorInvalidValue;
   }
 }
@@ -218,7 +274,7 @@ hipError_t launch_step_f32(int32_t tile, const StepArgs &a, hipStream_t s) {
 // then per replica the partial sum over this workgroup's 64 rows of
 // s_i (G_i + 2 h_i).  E = -1/2 sum_i s_i (G_i + 2 h_i) = Eq. (1).
 // ---------------------------------------------------------------------------
-using ECfg = F32Cfg<64, 64, 2, 2>;
+using ECfg = F32Cfg<64, 64, 2, 2, 32, 32>;
 
 __global__ __launch_bounds__(256) void energy_f32_partial_kernel(const float *J, const float *q,
                                                                  const float *h, float *part,
@@ -227,29 +283,28 @@ __global__ __launch_bounds__(256) void energy_f32_partial_kernel(const float *J,
   __shared__ float red[ECfg::WM][ECfg::BN];
   const int m0 = blockIdx.x * ECfg::BM;
   const int n0 = blockIdx.y * ECfg::BN;
-  floatx4 acc[ECfg::TM][ECfg::TN];
+  ECfg::acc_t acc[ECfg::TM][ECfg::TN];
   f32_mainloop<ECfg, true>(J, q, ld, ld, m0, n0, acc, smem);
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int wy = wave / ECfg::WN, wx = wave % ECfg::WN;
 #pragma unroll
   for (int j = 0; j < ECfg::TN; ++j) {
-    const int lcol = wx * ECfg::WTN + j * 16 + (lane & 15);
+    const int lcol = wx * ECfg::WTN + j * ECfg::MB + (lane % ECfg::MB);
     float c = 0.f;
 #pragma unroll
-    for (int i = 0; i < ECfg::TM; ++i) {
-      const int row = m0 + wy * ECfg::WTM + i * 16 + (lane >> 4) * 4;
-      const float4 q4 = *reinterpret_cast<const float4 *>(q + (size_t)(n0 + lcol) * ld + row);
-      float4 h4 = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (h) h4 = *reinterpret_cast<const float4 *>(h + row);
-      c += sign_pm1(q4.x) * (acc[i][j][0] + 2.f * h4.x);
-      c += sign_pm1(q4.y) * (acc[i][j][1] + 2.f * h4.y);
-      c += sign_pm1(q4.z) * (acc[i][j][2] + 2.f * h4.z);
-      c += sign_pm1(q4.w) * (acc[i][j][3] + 2.f * h4.w);
-    }
-    c += __shfl_xor(c, 16);
-    c += __shfl_xor(c, 32);
-    if (lane < 16) red[wy][lcol] = c;
+    for (int i = 0; i < ECfg::TM; ++i)
+#pragma unroll
+      for (int g = 0; g < ECfg::M::NACC / 4; ++g) {
+        const int row = m0 + wy * ECfg::WTM + i * ECfg::MB + g * 8 + (lane / ECfg::MB) * 4;
+        const floatx4 q4 = *reinterpret_cast<const floatx4 *>(q + (size_t)(n0 + lcol) * ld + row);
+        floatx4 h4 = {0.f, 0.f, 0.f, 0.f};
+        if (h) h4 = *reinterpret_cast<const floatx4 *>(h + row);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) c += sign_pm1(q4[v]) * (acc[i][j][4 * g + v] + 2.f * h4[v]);
+      }
+    for (int off = ECfg::MB; off < 64; off <<= 1) c += __shfl_xor(c, off);
+    if (lane < ECfg::MB) red[wy][lcol] = c;
   }
   __syncthreads();
   if (threadIdx.x < ECfg::BN) {
@@ -259,7 +314,6 @@ __global__ __launch_bounds__(256) void energy_f32_partial_kernel(const float *J,
     part[(size_t)blockIdx.x * r_pad + n0 + threadIdx.x] = s;
   }
 }
-
 __global__ void energy_f32_finalize_kernel(const float *part, int n_tiles, int r, int r_pad,
                                            double *e) {
   const int col = blockIdx.x * blockDim.x + threadIdx.x;

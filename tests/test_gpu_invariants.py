@@ -77,15 +77,17 @@ def test_resume_is_bit_identical():
     assert torch.equal(xa, xb) and torch.equal(pa, pb)
 
 
-def test_tiles_agree_on_early_steps():
-    # Every tile shape computes the same product; the accumulation order of
-    # the contraction is the same for all of them, so results are identical.
-    announce("tile shapes agree")
+@pytest.mark.parametrize("group", [(1, 2, 4, 5, 7, 8, 9, 11), (3, 6, 10, 12)])
+def test_tiles_agree(group):
+    # Tile shapes that use the same MFMA instruction add the contraction in
+    # the same order (slab depth and workgroup shape only regroup the
+    # work), so their trajectories are identical bit for bit.
+    announce(f"tile shapes agree {group}")
     n, r = 256, 128
     J = instances.make_pm1(n, 6)
     x0 = instances.make_x0(n, r, 6)
     ref = None
-    for tile in (1, 2, 3, 4, 5, 6):
+    for tile in group:
         x, p, e, info = _run(J, x0, 50, tile=tile)
         assert info["tile"] == tile
         if ref is None:
