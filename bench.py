@@ -68,6 +68,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--iters", type=int, default=ITERS, help=argparse.SUPPRESS)
+    ap.add_argument("--tile", type=int, default=0, help="step-kernel tile id (0 = automatic)")
+    ap.add_argument("--precision", default="fp32", help="fp32 | bf16x_fp8j | bf16x_bf16j | "
+                    "bf16x_hiloj | bf16x3_exactj (the headline line is fp32)")
+    ap.add_argument("--calib-copy-mb", type=int, default=0,
+                    help="first run one device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the replica-"
@@ -86,10 +91,16 @@ def main():
     si.load_library()
     dev = torch.device("cuda:0")
     iters = args.iters
+    if args.calib_copy_mb:
+        src = torch.ones(args.calib_copy_mb * 262144, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     Jn = instances.make_pm1(N, 0)
     J = torch.from_numpy(Jn).to(dev)
     x0 = torch.from_numpy(instances.make_x0(N, R, 0)).to(dev)
-    model = si.SpringIsing(J, x0, total_steps=iters)
+    model = si.SpringIsing(J, x0, total_steps=iters, tile=args.tile, precision=args.precision)
     info = model.info()
     stream = torch.cuda.current_stream()
     W = float(-np.triu(Jn.astype(np.float64), 1).sum())

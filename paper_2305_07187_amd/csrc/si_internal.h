@@ -12,7 +12,7 @@ namespace si {
 // Tile ids of the FP32 step kernel (see the tile table in si_step_f32.hip);
 // 0 selects automatically.
 constexpr int32_t TILE_AUTO = 0;
-constexpr int32_t TILE_F32_LAST = 12;
+constexpr int32_t TILE_F32_LAST = 24;
 
 struct TileShape {
   int32_t bm, bn;

@@ -47,9 +47,17 @@ struct MfmaF32<32> {
   }
 };
 
-template <int BM_, int BN_, int WM_, int WN_, int MB_, int BK_>
+template <int BM_, int BN_, int WM_, int WN_, int MB_, int BK_, int STAGES_ = 0, int KS_ = 1>
 struct F32Cfg {
   static constexpr int BM = BM_, BN = BN_, WM = WM_, WN = WN_, MB = MB_, BK = BK_;
+  // KS independent accumulators per output block, alternating over the
+  // four MFMAs of each contraction step (shorter dependency chains) and
+  // added at the end (direct-to-LDS pipeline only).
+  static constexpr int KS = KS_;
+  // STAGES = 0: slabs staged through registers into a padded double buffer.
+  // STAGES >= 3: slabs copied straight into an LDS ring of STAGES slots by
+  // direct-to-LDS loads, STAGES - 1 slabs in flight.
+  static constexpr int STAGES = STAGES_;
   static constexpr int LDK = BK + 4;  // padded LDS row: conflict-free 128-bit reads
   static constexpr int WTM = BM / WM, WTN = BN / WN;
   static constexpr int TM = WTM / MB, TN = WTN / MB;
@@ -65,8 +73,139 @@ struct F32Cfg {
   static_assert(A_F4 >= 1 && B_F4 >= 1 && BM * BK / 4 % NT == 0 && BN * BK / 4 % NT == 0,
                 "slab loads");
   static_assert(BK % KSTEP == 0, "slab depth");
-  static constexpr int LDS_FLOATS = 2 * (BM + BN) * LDK;
+  static constexpr int LDS_FLOATS = STAGES ? STAGES * (BM + BN) * BK : 2 * (BM + BN) * LDK;
 };
+
+typedef __attribute__((address_space(3))) void lds_void_t;
+typedef __attribute__((address_space(1))) const void gbl_void_t;
+
+// Wait until at most N vector-memory operations of this wave are in flight,
+// then synchronise the workgroup.  The memory clobber keeps every LDS access
+// on its side of the barrier.
+template <int N>
+__device__ __forceinline__ void wait_vm_barrier() {
+  asm volatile("s_waitcnt vmcnt(%0)\n\ts_barrier" ::"n"(N) : "memory");
+}
+
+// Direct-to-LDS pipeline.  Each slab row of BK floats is stored unpadded;
+// its 16-byte chunk c sits at position c ^ (row & 7), which spreads the
+// 128-bit fragment reads of eight consecutive rows over distinct banks.  A
+// direct-to-LDS load writes 16 bytes per lane at consecutive addresses, so
+// lane L fetches the global chunk that belongs at its destination.
+template <class C>
+__device__ __forceinline__ void f32_mainloop_dma(const float *__restrict__ A,
+                                                 const float *__restrict__ B, int ld, int K,
+                                                 int m0, int n0,
+                                                 typename C::acc_t (&acc)[C::TM][C::TN],
+                                                 float *smem) {
+  constexpr int S = C::STAGES;
+  constexpr int NW = C::NT / 64;
+  constexpr int CH = C::BK / 4;            // 16-byte chunks per row
+  constexpr int RPD = 64 / CH;             // rows written by one wave-wide load
+  constexpr int A_DMA = C::BM / RPD / NW;  // loads per wave per slab
+  constexpr int B_DMA = C::BN / RPD / NW;
+  constexpr int L = A_DMA + B_DMA;
+  constexpr int SLAB = (C::BM + C::BN) * C::BK;  // floats per ring slot
+  static_assert(A_DMA >= 1 && B_DMA >= 1 && C::BM % (RPD * NW) == 0 && C::BN % (RPD * NW) == 0,
+                "direct-to-LDS slab split");
+  static_assert((S - 2) * L <= 63, "vmcnt range");
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wy = wave / C::WN, wx = wave % C::WN;
+  const int lrow = lane % C::MB, lk = (lane / C::MB) * 4;
+  const int drow = lane / CH, dch = lane % CH;
+
+  typename C::acc_t part[C::TM][C::TN][C::KS];
+#pragma unroll
+  for (int i = 0; i < C::TM; ++i)
+#pragma unroll
+    for (int j = 0; j < C::TN; ++j)
+#pragma unroll
+      for (int u = 0; u < C::KS; ++u)
+#pragma unroll
+        for (int v = 0; v < C::M::NACC; ++v) part[i][j][u][v] = 0.f;
+
+  // global source of this lane for each of its loads (k offset added later)
+  const float *srcA[A_DMA];
+  const float *srcB[B_DMA];
+#pragma unroll
+  for (int d = 0; d < A_DMA; ++d) {
+    const int row = (wave * A_DMA + d) * RPD + drow;
+    srcA[d] = A + (size_t)(m0 + row) * ld + ((dch ^ (row & 7)) * 4);
+  }
+#pragma unroll
+  for (int d = 0; d < B_DMA; ++d) {
+    const int row = (wave * B_DMA + d) * RPD + drow;
+    srcB[d] = B + (size_t)(n0 + row) * ld + ((dch ^ (row & 7)) * 4);
+  }
+  auto issue = [&](int kt, int slot) {
+    float *st = smem + slot * SLAB;
+#pragma unroll
+    for (int d = 0; d < A_DMA; ++d)
+      __builtin_amdgcn_global_load_lds((gbl_void_t *)(srcA[d] + kt * C::BK),
+                                       (lds_void_t *)(st + (wave * A_DMA + d) * RPD * C::BK), 16,
+                                       0, 0);
+#pragma unroll
+    for (int d = 0; d < B_DMA; ++d)
+      __builtin_amdgcn_global_load_lds(
+          (gbl_void_t *)(srcB[d] + kt * C::BK),
+          (lds_void_t *)(st + (C::BM + (wave * B_DMA + d) * RPD) * C::BK), 16, 0, 0);
+  };
+
+  const int nk = K / C::BK;
+#pragma unroll
+  for (int s = 0; s < S - 1; ++s)
+    if (s < nk) issue(s, s);
+  const int ra = wy * C::WTM + lrow, rb = wx * C::WTN + lrow;  // fragment rows (i = j = 0)
+  for (int kt = 0; kt < nk; ++kt) {
+    if (kt + S - 1 < nk) {
+      wait_vm_barrier<(S - 2) * L>();
+      issue(kt + S - 1, (kt + S - 1) % S);
+    } else {
+      wait_vm_barrier<0>();
+    }
+    const float *st = smem + (kt % S) * SLAB;
+    // fragments of the next contraction step are read while the MFMAs of
+    // the current one run
+    floatx4 a[2][C::TM], b[2][C::TN];
+    auto frag = [&](int kk, floatx4 (&fa)[C::TM], floatx4 (&fb)[C::TN]) {
+      const int ch = (kk + lk) >> 2;
+#pragma unroll
+      for (int i = 0; i < C::TM; ++i) {
+        const int r = ra + i * C::MB;
+        fa[i] = *reinterpret_cast<const floatx4 *>(st + r * C::BK + ((ch ^ (r & 7)) << 2));
+      }
+#pragma unroll
+      for (int j = 0; j < C::TN; ++j) {
+        const int r = rb + j * C::MB;
+        fb[j] = *reinterpret_cast<const floatx4 *>(st + (C::BM + r) * C::BK + ((ch ^ (r & 7)) << 2));
+      }
+    };
+    frag(0, a[0], b[0]);
+#pragma unroll
+    for (int kk = 0; kk < C::BK; kk += C::KSTEP) {
+      const int cur = (kk / C::KSTEP) & 1;
+      if (kk + C::KSTEP < C::BK) frag(kk + C::KSTEP, a[cur ^ 1], b[cur ^ 1]);
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int i = 0; i < C::TM; ++i)
+#pragma unroll
+          for (int j = 0; j < C::TN; ++j)
+            part[i][j][s % C::KS] =
+                C::M::mma(a[cur][i][s], b[cur][j][s], part[i][j][s % C::KS]);
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < C::TM; ++i)
+#pragma unroll
+    for (int j = 0; j < C::TN; ++j) {
+      acc[i][j] = part[i][j][0];
+#pragma unroll
+      for (int u = 1; u < C::KS; ++u) acc[i][j] += part[i][j][u];
+    }
+  // all waves done reading the ring before the caller reuses LDS
+  wait_vm_barrier<0>();
+}
 
 __device__ __forceinline__ float sign_pm1(float x) { return x < 0.f ? -1.f : 1.f; }
 
@@ -181,32 +320,51 @@ __global__ __launch_bounds__(C::NT) void step_f32_kernel(StepArgs a) {
   __shared__ __attribute__((aligned(16))) float smem[C::LDS_FLOATS];
   const int m0 = blockIdx.x * C::BM;
   const int n0 = blockIdx.y * C::BN;
-  typename C::acc_t acc[C::TM][C::TN];
-  f32_mainloop<C, false>(a.J, a.q_in, a.ld, a.n_pad, m0, n0, acc, smem);
-
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int wy = wave / C::WN, wx = wave % C::WN;
-  const float dt = a.dt[a.t], zeta = a.zeta[a.t];
+  constexpr int G = C::M::NACC / 4;
+  // The state this lane updates is loaded before the contraction so that
+  // its latency overlaps the matrix work.
+  floatx4 q4[C::TM][G][C::TN], p4[C::TM][G][C::TN], h4[C::TM][G];
 #pragma unroll
-  for (int i = 0; i < C::TM; ++i) {
+  for (int i = 0; i < C::TM; ++i)
 #pragma unroll
-    for (int g = 0; g < C::M::NACC / 4; ++g) {
+    for (int g = 0; g < G; ++g) {
       const int row = m0 + wy * C::WTM + i * C::MB + g * 8 + (lane / C::MB) * 4;
-      floatx4 h4 = {0.f, 0.f, 0.f, 0.f};
-      if (a.h) h4 = *reinterpret_cast<const floatx4 *>(a.h + row);
+      h4[i][g] = floatx4{0.f, 0.f, 0.f, 0.f};
+      if (a.h) h4[i][g] = *reinterpret_cast<const floatx4 *>(a.h + row);
 #pragma unroll
       for (int j = 0; j < C::TN; ++j) {
         const int col = n0 + wx * C::WTN + j * C::MB + (lane % C::MB);
         const size_t off = (size_t)col * a.ld + row;
-        const floatx4 q4 = *reinterpret_cast<const floatx4 *>(a.q_in + off);
-        const floatx4 p4 = *reinterpret_cast<const floatx4 *>(a.p_in + off);
+        q4[i][g][j] = *reinterpret_cast<const floatx4 *>(a.q_in + off);
+        p4[i][g][j] = *reinterpret_cast<const floatx4 *>(a.p_in + off);
+      }
+    }
+
+  typename C::acc_t acc[C::TM][C::TN];
+  if constexpr (C::STAGES > 0)
+    f32_mainloop_dma<C>(a.J, a.q_in, a.ld, a.n_pad, m0, n0, acc, smem);
+  else
+    f32_mainloop<C, false>(a.J, a.q_in, a.ld, a.n_pad, m0, n0, acc, smem);
+
+  const float dt = a.dt[a.t], zeta = a.zeta[a.t];
+#pragma unroll
+  for (int i = 0; i < C::TM; ++i) {
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      const int row = m0 + wy * C::WTM + i * C::MB + g * 8 + (lane / C::MB) * 4;
+#pragma unroll
+      for (int j = 0; j < C::TN; ++j) {
+        const int col = n0 + wx * C::WTN + j * C::MB + (lane % C::MB);
+        const size_t off = (size_t)col * a.ld + row;
         floatx4 qn, pn;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           float qv, pv;
-          update<ORDER, WALL>(q4[v], p4[v], acc[i][j][4 * g + v] + h4[v], dt, zeta, a.k, a.inv_m,
-                              a.qmax, a.pmax, qv, pv);
+          update<ORDER, WALL>(q4[i][g][j][v], p4[i][g][j][v], acc[i][j][4 * g + v] + h4[i][g][v],
+                              dt, zeta, a.k, a.inv_m, a.qmax, a.pmax, qv, pv);
           qn[v] = qv;
           pn[v] = pv;
         }
@@ -217,26 +375,40 @@ __global__ __launch_bounds__(C::NT) void step_f32_kernel(StepArgs a) {
   }
 }
 
-// Tile table: id, BM, BN, waves (WM x WN), MFMA block edge, slab depth BK.
-#define SI_F32_TILES(X)             \
-  X(1, 64, 128, 2, 2, 32, 32)       \
-  X(2, 64, 64, 2, 2, 32, 32)        \
-  X(3, 32, 32, 2, 2, 16, 32)        \
-  X(4, 128, 64, 2, 2, 32, 32)       \
-  X(5, 128, 128, 2, 2, 32, 32)      \
-  X(6, 32, 64, 2, 2, 16, 32)        \
-  X(7, 64, 128, 2, 2, 32, 64)       \
-  X(8, 64, 128, 2, 4, 32, 32)       \
-  X(9, 64, 64, 2, 2, 32, 64)        \
-  X(10, 64, 128, 2, 2, 16, 32)      \
-  X(11, 128, 128, 2, 4, 32, 32)     \
-  X(12, 64, 64, 2, 2, 16, 32)
+// Tile table: id, BM, BN, waves (WM x WN), MFMA block edge, slab depth BK,
+// LDS stages (0: register-staged double buffer; >= 3: direct-to-LDS ring).
+#define SI_F32_TILES(X)                \
+  X(1, 64, 128, 2, 2, 32, 32, 0, 1)    \
+  X(2, 64, 64, 2, 2, 32, 32, 0, 1)        \
+  X(3, 32, 32, 2, 2, 16, 32, 0, 1)        \
+  X(4, 128, 64, 2, 2, 32, 32, 0, 1)       \
+  X(5, 128, 128, 2, 2, 32, 32, 0, 1)      \
+  X(6, 32, 64, 2, 2, 16, 32, 0, 1)        \
+  X(7, 64, 128, 2, 2, 32, 64, 0, 1)       \
+  X(8, 64, 128, 2, 4, 32, 32, 0, 1)       \
+  X(9, 64, 64, 2, 2, 32, 64, 0, 1)        \
+  X(10, 64, 128, 2, 2, 16, 32, 0, 1)      \
+  X(11, 128, 128, 2, 4, 32, 32, 0, 1)     \
+  X(12, 64, 64, 2, 2, 16, 32, 0, 1)       \
+  X(13, 64, 64, 2, 2, 32, 32, 3, 1)       \
+  X(14, 64, 64, 2, 2, 32, 32, 4, 1)       \
+  X(15, 64, 64, 2, 2, 32, 64, 3, 1)       \
+  X(16, 64, 128, 2, 2, 32, 32, 4, 1)      \
+  X(17, 64, 64, 2, 2, 32, 32, 6, 1)       \
+  X(18, 128, 64, 2, 2, 32, 32, 4, 1)      \
+  X(19, 64, 64, 2, 2, 32, 32, 4, 2)    \
+  X(20, 64, 64, 2, 2, 32, 32, 4, 4)    \
+  X(21, 64, 64, 2, 1, 32, 32, 4, 1)    \
+  X(22, 64, 64, 2, 1, 32, 32, 4, 2)    \
+  X(23, 64, 64, 2, 2, 32, 64, 3, 2)    \
+  X(24, 64, 128, 2, 2, 32, 32, 4, 2)
 
 TileShape tile_shape(int32_t tile) {
   switch (tile) {
-#define SI_SHAPE(id, bm, bn, wm, wn, mb, bk) \
-  case id:                                   \
-    return {bm, bn, "step_f32_" #bm "x" #bn "_w" #wm "x" #wn "_mfma" #mb "_k" #bk};
+#define SI_SHAPE(id, bm, bn, wm, wn, mb, bk, st, ks) \
+  case id:                                           \
+    return {bm, bn,                                  \
+            "step_f32_" #bm "x" #bn "_w" #wm "x" #wn "_mfma" #mb "_k" #bk "_s" #st "_a" #ks};
     SI_F32_TILES(SI_SHAPE)
 #undef SI_SHAPE
     default: return {0, 0, "invalid"};
@@ -260,9 +432,9 @@ static hipError_t launch_cfg(const StepArgs &a, hipStream_t s) {
 
 hipError_t launch_step_f32(int32_t tile, const StepArgs &a, hipStream_t s) {
   switch (tile) {
-#define SI_LAUNCH(id, bm, bn, wm, wn, mb, bk) \
-  case id:                                    \
-    return launch_cfg<F32Cfg<bm, bn, wm, wn, mb, bk>>(a, s);
+#define SI_LAUNCH(id, bm, bn, wm, wn, mb, bk, st, ks) \
+  case id:                                            \
+    return launch_cfg<F32Cfg<bm, bn, wm, wn, mb, bk, st, ks>>(a, s);
     SI_F32_TILES(SI_LAUNCH)
 #undef SI_LAUNCH
     default: return hipErrorInvalidValue;
