@@ -11,6 +11,13 @@ then the int32 Ising energy of sign(q) for every replica.
 One benchmark step = one such full run (reset to x0, 10000 iterations,
 energy readout).  Reported value: spin-updates/s = N * R * iterations / s.
 
+Beside the headline line the same run is timed in the BF16 precision forms,
+and time-to-target-energy is measured: the target is the 1% quantile of the
+FP32 final energies; each form runs the same schedule with the exact energy
+of every replica checked every 50 steps (check cost included, timed with
+HIP events on the stream the kernels run on) and its time-to-target is the
+event time of the first check with a replica at or below the target.
+
     python bench.py [--steps K] [--warmup W] [--gpus 1]
 """
 from __future__ import annotations
@@ -26,9 +33,12 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 N, R, ITERS = 2000, 1024, 10000
+CHECK_EVERY = 50
 # MI355X published peaks
 PEAK_FP32_MFMA_TFLOPS = 157.3
+PEAK_BF16_MFMA_TFLOPS = 2500.0
 PEAK_HBM_GBS = 8000.0
+FORMS = ["bf16x_fp8j", "bf16x_bf16j", "bf16x3_exactj"]
 
 
 def cpu_baseline(budget_s: float = 15.0):
@@ -61,12 +71,61 @@ def cpu_baseline(budget_s: float = 15.0):
                       f"{el:.1f} s), extrapolated per iteration"}
 
 
+def timed_runs(model, x0, iters, steps, warmup, stream):
+    """Full runs (reset, iters steps, energy); per-run HIP events bracket the
+    step launches.  Returns (elapsed_s, per-launch us, last energies)."""
+    import torch
+
+    def one_run(ev=None):
+        model.set_state(x0, None, 0)
+        if ev is not None:
+            ev[0].record(stream)
+        model.run(iters)
+        if ev is not None:
+            ev[1].record(stream)
+        return model.energy()
+
+    for _ in range(warmup):
+        one_run()
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(steps)]
+    t0 = time.perf_counter()
+    energies = None
+    for k in range(steps):
+        energies = one_run(evs[k])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    run_ms = [a.elapsed_time(b) for a, b in evs]
+    kernel_us = 1000.0 * sum(run_ms) / (len(run_ms) * iters)
+    return elapsed, kernel_us, energies
+
+
+def run_with_checks(si, model, x0, iters, every, stream):
+    """One run with the exact energy of all replicas every `every` steps."""
+    import torch
+    checks = iters // every
+    E = torch.empty(checks, model.r, dtype=torch.int32, device=x0.device)
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(checks + 1)]
+    model.set_state(x0, None, 0)
+    torch.cuda.synchronize()
+    evs[0].record(stream)
+    for c in range(checks):
+        model.run(every)
+        si.spring_ising_energy(model.ctx, E[c], None)
+        evs[c + 1].record(stream)
+    torch.cuda.synchronize()
+    times = [evs[0].elapsed_time(e) for e in evs[1:]]
+    return E.cpu().numpy(), times
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-forms", action="store_true", help="skip the precision-form lines")
     ap.add_argument("--iters", type=int, default=ITERS, help=argparse.SUPPRESS)
     ap.add_argument("--tile", type=int, default=0, help="step-kernel tile id (0 = automatic)")
     ap.add_argument("--precision", default="fp32", help="fp32 | bf16x_fp8j | bf16x_bf16j | "
@@ -100,41 +159,19 @@ def main():
     Jn = instances.make_pm1(N, 0)
     J = torch.from_numpy(Jn).to(dev)
     x0 = torch.from_numpy(instances.make_x0(N, R, 0)).to(dev)
-    model = si.SpringIsing(J, x0, total_steps=iters, tile=args.tile, precision=args.precision)
-    info = model.info()
     stream = torch.cuda.current_stream()
     W = float(-np.triu(Jn.astype(np.float64), 1).sum())
 
-    def one_run(ev=None):
-        model.set_state(x0, None, 0)
-        if ev is not None:
-            ev[0].record(stream)
-        model.run(iters)
-        if ev is not None:
-            ev[1].record(stream)
-        return model.energy()
-
-    for _ in range(args.warmup):
-        one_run()
-    torch.cuda.synchronize()
-
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-           for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    energies = None
-    for k in range(args.steps):
-        energies = one_run(evs[k])
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    run_ms = [a.elapsed_time(b) for a, b in evs]
-    kernel_us = 1000.0 * sum(run_ms) / (len(run_ms) * iters)  # per step launch
-
+    model = si.SpringIsing(J, x0, total_steps=iters, tile=args.tile, precision=args.precision)
+    info = model.info()
+    elapsed, kernel_us, energies = timed_runs(model, x0, iters, args.steps, args.warmup, stream)
     e = energies.cpu().numpy().astype(np.float64)
     cuts = (W - e) / 2
     flops = 2.0 * N * N * R
-    achieved_tflops = flops / (kernel_us * 1e-6) / 1e12
+    achieved = flops / (kernel_us * 1e-6) / 1e12
     value = N * R * iters * args.steps / elapsed
+    fp32_line = args.precision == "fp32"
+    peak = PEAK_FP32_MFMA_TFLOPS if fp32_line else PEAK_BF16_MFMA_TFLOPS
     out = {
         "metric": "spin-updates/s (N*R*steps/s) at N=2000",
         "value": value,
@@ -146,22 +183,57 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f32" if fp32_line else "bf16",
         "data": "synthetic",
         "config": {"workload": f"K2000-shaped +-1 complete graph, N={N}, R={R} replicas, "
-                               f"{iters} iterations, paper linear zeta schedule, FP32",
-                   "n": N, "replicas": R, "iterations": iters, "precision": "fp32",
+                               f"{iters} iterations, paper linear zeta schedule, "
+                               f"{args.precision}",
+                   "n": N, "replicas": R, "iterations": iters, "precision": args.precision,
                    "kernel": info["kernel_name"]},
-        "roofline": {"bound": "mfma", "achieved": achieved_tflops,
-                     "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved_tflops / PEAK_FP32_MFMA_TFLOPS, "traffic": None,
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                     "frac": achieved / peak, "traffic": None,
                      "kernel": info["kernel_name"], "avg_launch_us": kernel_us,
                      "algorithmic_flop_per_launch": flops},
         "result": {"best_cut": float(cuts.max()), "mean_cut": float(cuts.mean()),
                    "best_energy": int(e.min()), "mean_energy": float(e.mean())},
     }
+
+    if fp32_line and not args.no_forms and iters % CHECK_EVERY == 0:
+        from scipy.stats import ks_2samp
+        target = float(np.sort(e)[max(0, int(0.01 * R) - 1)])  # 1% quantile (10th best)
+        forms = {}
+        for name in ["fp32"] + FORMS:
+            m = model if name == "fp32" else si.SpringIsing(J, x0, total_steps=iters,
+                                                              precision=name)
+            if name == "fp32":
+                el, us, en = elapsed / args.steps, kernel_us, e
+            else:
+                el_tot, us, en_t = timed_runs(m, x0, iters, args.steps, 1, stream)
+                el, en = el_tot / args.steps, en_t.cpu().numpy().astype(np.float64)
+            Ec, times = run_with_checks(si, m, x0, iters, CHECK_EVERY, stream)
+            hit = np.nonzero(Ec.min(axis=1) <= target)[0]
+            frac_at_end = float((en <= target).mean())
+            rec = {"spin_updates_per_s": N * R * iters / el, "avg_launch_us": us,
+                   "kernel": m.info()["kernel_name"],
+                   "ttt_s": float(times[hit[0]]) / 1000.0 if len(hit) else None,
+                   "ttt_step": int((hit[0] + 1) * CHECK_EVERY) if len(hit) else None,
+                   "mean_energy": float(en.mean()), "best_energy": float(en.min()),
+                   "frac_at_or_below_target": frac_at_end}
+            if name != "fp32":
+                rec["ks_pvalue_vs_fp32"] = float(ks_2samp(en, e).pvalue)
+                rec["mean_diff_in_se"] = float((en.mean() - e.mean()) /
+                                               np.sqrt(en.var() / R + e.var() / R))
+                m.close()
+            forms[name] = rec
+        t32 = forms["fp32"]["ttt_s"]
+        for name in FORMS:
+            tf = forms[name]["ttt_s"]
+            forms[name]["ttt_speedup_vs_fp32"] = (t32 / tf) if (t32 and tf) else None
+        out["time_to_target"] = {"target_energy": target, "check_every": CHECK_EVERY,
+                                 "forms": forms}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
+    model.close()
     print(json.dumps(out))
 
 

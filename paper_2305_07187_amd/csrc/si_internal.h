@@ -41,7 +41,7 @@ struct StepArgs {
 hipError_t launch_step_f32(int32_t tile, const StepArgs &a, hipStream_t s);
 
 // Step on the BF16 matrix cores (precision forms).
-constexpr int32_t TILE_BF16_LAST = 6;
+constexpr int32_t TILE_BF16_LAST = 13;
 TileShape tile_shape_bf16(int32_t tile);
 struct BStepArgs {
   const void *Ja;         // J plane: bf16 or fp8 [n_pad][n_pad]
@@ -57,6 +57,7 @@ struct BStepArgs {
   int32_t order, wall;
 };
 hipError_t launch_step_bf16(int32_t tile, int32_t precision, const BStepArgs &a, hipStream_t s);
+bool tile_valid_bf16(int32_t tile, int32_t precision);
 hipError_t launch_pack_j_lowp(const float *J, int64_t total, int32_t precision, void *out_a,
                               void *out_b, hipStream_t s);
 hipError_t launch_split_planes(const float *q, uint16_t *planes, int64_t total, int32_t nplanes,

@@ -159,11 +159,23 @@ static TileShape shape_of(int32_t precision, int32_t tile) {
   return precision == SI_PREC_FP32 ? tile_shape(tile) : tile_shape_bf16(tile);
 }
 
-static int32_t choose_tile_bf16(int32_t n, int32_t r, int num_cus) {
-  const int32_t order[] = {1, 2, 3, 4};
+static int32_t choose_tile_bf16(int32_t n, int32_t r, int num_cus, int32_t precision) {
+  // Preference from a tile sweep at N=2000, R=1024 on MI355X (direct-to-LDS
+  // rings first; register-staged tiles as the fallback for small problems).
+  static const int32_t pref_bf16j[] = {8, 7, 11, 10, 1, 2, 3};
+  static const int32_t pref_fp8j[] = {9, 13, 1, 6, 2, 3};
+  static const int32_t pref_hilo[] = {7, 10, 11, 1, 2, 3};
+  static const int32_t pref_exact[] = {11, 8, 7, 1, 2, 3};
+  const int32_t *order = pref_bf16j;
+  int count = 7;
+  if (precision == SI_PREC_BF16X_FP8J) { order = pref_fp8j; count = 6; }
+  if (precision == SI_PREC_BF16X_HILOJ) { order = pref_hilo; count = 6; }
+  if (precision == SI_PREC_BF16X3_EXACTJ) { order = pref_exact; count = 6; }
   int32_t best = 1;
   int64_t best_tiles = -1;
-  for (int32_t t : order) {
+  for (int c = 0; c < count; ++c) {
+    const int32_t t = order[c];
+    if (!tile_valid_bf16(t, precision)) continue;
     TileShape ts = tile_shape_bf16(t);
     const int64_t np = round_up(n, ts.bm > 64 ? ts.bm : 64);
     const int64_t rp = round_up(r, ts.bn > 64 ? ts.bn : 64);
@@ -254,7 +266,13 @@ si_status spring_ising_init(si_ctx **out, int32_t n, int32_t r, const float *J, 
 
   const bool lowp = prm->precision != SI_PREC_FP32;
   c->tile = prm->tile ? prm->tile
-                      : (lowp ? choose_tile_bf16(n, r, c->num_cus) : choose_tile(n, r, c->num_cus));
+                      : (lowp ? choose_tile_bf16(n, r, c->num_cus, prm->precision)
+                              : choose_tile(n, r, c->num_cus));
+  if (lowp && !tile_valid_bf16(c->tile, prm->precision)) {
+    const int32_t bad = c->tile;
+    delete c;
+    return fail(SI_ERR_INVALID, "init: tile %d cannot run precision %d", bad, prm->precision);
+  }
   const TileShape ts = shape_of(prm->precision, c->tile);
   c->n_pad = (int32_t)round_up(n, ts.bm > 128 ? ts.bm : 128);
   c->r_pad = (int32_t)round_up(r, ts.bn > 64 ? ts.bn : 64);

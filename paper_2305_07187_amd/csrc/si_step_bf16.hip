@@ -186,6 +186,201 @@ __device__ __forceinline__ void bf16_mainloop(const BStepArgs &a, int m0, int n0
   }
 }
 
+// ---------------------------------------------------------------------------
+// Direct-to-LDS pipeline for the BF16 forms.  STAGES slots of LDS hold the
+// J plane(s) and the q plane(s) of one slab each; STAGES - 1 slabs are in
+// flight.  Rows are stored unpadded with the 16-byte chunk c of row r at
+// position c ^ (r & 7) (rows of 128 or 256 bytes), which keeps the 128-bit
+// fragment reads of eight consecutive rows on distinct banks.  FP8 J stays
+// one byte per coupling in LDS and is widened to BF16 by the hardware FP8
+// conversion when the fragment is read.
+//
+// Contraction slots: the MFMAs run in pairs over 32 indices; in MFMA s of a
+// pair, lane half h = l/32 holds indices kk + 16h + 8s .. +7.
+// ---------------------------------------------------------------------------
+typedef __attribute__((address_space(3))) void lds_void_b;
+typedef __attribute__((address_space(1))) const void gbl_void_b;
+
+template <int N>
+__device__ __forceinline__ void wait_vm_barrier_b() {
+  asm volatile("s_waitcnt vmcnt(%0)\n\ts_barrier" ::"n"(N) : "memory");
+}
+
+template <int BM_, int BN_, int WM_, int WN_, int BK_, int JFMT_, int QP_, int STAGES_>
+struct Bf16DmaCfg {
+  static constexpr int BM = BM_, BN = BN_, WM = WM_, WN = WN_, BK = BK_;
+  static constexpr int JFMT = JFMT_, QP = QP_, STAGES = STAGES_;
+  static constexpr int JP = JFMT == 2 ? 2 : 1;
+  static constexpr int EA = JFMT == 1 ? 1 : 2;  // bytes per J element in LDS
+  static constexpr int MB = 32;
+  static constexpr int WTM = BM / WM, WTN = BN / WN;
+  static constexpr int TM = WTM / MB, TN = WTN / MB;
+  static constexpr int NT = 64 * WM * WN, NW = NT / 64;
+  static constexpr int ROWA = BK * EA, ROWB = BK * 2;  // bytes per row
+  static constexpr int CHA = ROWA / 16, CHB = ROWB / 16;
+  static constexpr int RPDA = 64 / CHA, RPDB = 64 / CHB;  // rows per wave-wide load
+  static constexpr int A_DMA = BM / RPDA / NW, B_DMA = BN / RPDB / NW;
+  static constexpr int L = JP * A_DMA + QP * B_DMA;  // loads per wave per slab
+  static constexpr int A_BYTES = BM * ROWA, B_BYTES = BN * ROWB;
+  static constexpr int SLOT = JP * A_BYTES + QP * B_BYTES;
+  static constexpr int LDS_BYTES = STAGES * SLOT;
+  static_assert(CHA >= 8 && CHB >= 8, "rows of at least 128 bytes for the chunk swizzle");
+  static_assert(A_DMA >= 1 && B_DMA >= 1 && BM % (RPDA * NW) == 0 && BN % (RPDB * NW) == 0,
+                "direct-to-LDS slab split");
+  static_assert(TM >= 1 && TN >= 1 && BK % 32 == 0, "tile");
+  static_assert(STAGES >= 3 && (STAGES - 2) * L <= 63, "pipeline depth");
+};
+
+__device__ __forceinline__ uint32_t pack_hi16(float lo, float hi) {
+  return (__float_as_uint(hi) & 0xFFFF0000u) | (__float_as_uint(lo) >> 16);
+}
+
+// 8 FP8 e4m3 values (two words) -> 8 BF16 (exact: e4m3 has 4 significant bits)
+__device__ __forceinline__ bf16x8 fp8x8_to_bf16x8(uint32_t w0, uint32_t w1) {
+  typedef float floatx2 __attribute__((ext_vector_type(2)));
+  const floatx2 a = __builtin_amdgcn_cvt_pk_f32_fp8((int)w0, false);
+  const floatx2 b = __builtin_amdgcn_cvt_pk_f32_fp8((int)w0, true);
+  const floatx2 c = __builtin_amdgcn_cvt_pk_f32_fp8((int)w1, false);
+  const floatx2 d = __builtin_amdgcn_cvt_pk_f32_fp8((int)w1, true);
+  uintx4 u;
+  u[0] = pack_hi16(a[0], a[1]);
+  u[1] = pack_hi16(b[0], b[1]);
+  u[2] = pack_hi16(c[0], c[1]);
+  u[3] = pack_hi16(d[0], d[1]);
+  return __builtin_bit_cast(bf16x8, u);
+}
+
+template <class C>
+__device__ __forceinline__ void bf16_mainloop_dma(const BStepArgs &a, int m0, int n0,
+                                                  floatx16 (&acc)[C::TM][C::TN],
+                                                  uint8_t *smem) {
+  constexpr int S = C::STAGES;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wy = wave / C::WN, wx = wave % C::WN;
+  const int lrow = lane % 32, h = lane / 32;
+  const int ld = a.ld;
+
+#pragma unroll
+  for (int i = 0; i < C::TM; ++i)
+#pragma unroll
+    for (int j = 0; j < C::TN; ++j)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.f;
+
+  // per-lane global sources (byte pointers), k offset added per slab
+  const uint8_t *srcA[C::JP][C::A_DMA];
+  const uint8_t *srcB[C::QP][C::B_DMA];
+  {
+    const int drow = lane / C::CHA, dch = lane % C::CHA;
+#pragma unroll
+    for (int pl = 0; pl < C::JP; ++pl) {
+      const uint8_t *base = reinterpret_cast<const uint8_t *>(pl == 0 ? a.Ja : a.Jb);
+#pragma unroll
+      for (int d = 0; d < C::A_DMA; ++d) {
+        const int row = (wave * C::A_DMA + d) * C::RPDA + drow;
+        srcA[pl][d] = base + ((size_t)(m0 + row) * ld) * C::EA + (dch ^ (row & 7)) * 16;
+      }
+    }
+  }
+  {
+    const int drow = lane / C::CHB, dch = lane % C::CHB;
+#pragma unroll
+    for (int pl = 0; pl < C::QP; ++pl) {
+      const uint8_t *base =
+          reinterpret_cast<const uint8_t *>(a.qb_in + (size_t)pl * a.plane_stride);
+#pragma unroll
+      for (int d = 0; d < C::B_DMA; ++d) {
+        const int row = (wave * C::B_DMA + d) * C::RPDB + drow;
+        srcB[pl][d] = base + ((size_t)(n0 + row) * ld) * 2 + (dch ^ (row & 7)) * 16;
+      }
+    }
+  }
+  auto issue = [&](int kt, int slot) {
+    uint8_t *st = smem + slot * C::SLOT;
+#pragma unroll
+    for (int pl = 0; pl < C::JP; ++pl)
+#pragma unroll
+      for (int d = 0; d < C::A_DMA; ++d)
+        __builtin_amdgcn_global_load_lds(
+            (gbl_void_b *)(srcA[pl][d] + (size_t)kt * C::ROWA),
+            (lds_void_b *)(st + pl * C::A_BYTES + (wave * C::A_DMA + d) * C::RPDA * C::ROWA), 16,
+            0, 0);
+#pragma unroll
+    for (int pl = 0; pl < C::QP; ++pl)
+#pragma unroll
+      for (int d = 0; d < C::B_DMA; ++d)
+        __builtin_amdgcn_global_load_lds(
+            (gbl_void_b *)(srcB[pl][d] + (size_t)kt * C::ROWB),
+            (lds_void_b *)(st + C::JP * C::A_BYTES + pl * C::B_BYTES +
+                           (wave * C::B_DMA + d) * C::RPDB * C::ROWB),
+            16, 0, 0);
+  };
+
+  const int nk = a.n_pad / C::BK;
+#pragma unroll
+  for (int s = 0; s < S - 1; ++s)
+    if (s < nk) issue(s, s);
+  for (int kt = 0; kt < nk; ++kt) {
+    if (kt + S - 1 < nk) {
+      wait_vm_barrier_b<(S - 2) * C::L>();
+      issue(kt + S - 1, (kt + S - 1) % S);
+    } else {
+      wait_vm_barrier_b<0>();
+    }
+    const uint8_t *st = smem + (kt % S) * C::SLOT;
+#pragma unroll
+    for (int kk = 0; kk < C::BK; kk += 32) {
+      bf16x8 fa[C::JP][C::TM][2], fb[C::QP][C::TN][2];
+#pragma unroll
+      for (int i = 0; i < C::TM; ++i) {
+        const int r = wy * C::WTM + i * 32 + lrow;
+        if (C::JFMT == 1) {
+          const int ch = (kk + 16 * h) / 16;  // 16 fp8 per chunk
+          const uintx4 w = *reinterpret_cast<const uintx4 *>(st + r * C::ROWA +
+                                                             ((ch ^ (r & 7)) << 4));
+          fa[0][i][0] = fp8x8_to_bf16x8(w[0], w[1]);
+          fa[0][i][1] = fp8x8_to_bf16x8(w[2], w[3]);
+        } else {
+#pragma unroll
+          for (int pl = 0; pl < C::JP; ++pl)
+#pragma unroll
+            for (int sidx = 0; sidx < 2; ++sidx) {
+              const int ch = (kk + 16 * h + 8 * sidx) / 8;  // 8 bf16 per chunk
+              fa[pl][i][sidx] = *reinterpret_cast<const bf16x8 *>(
+                  st + pl * C::A_BYTES + r * C::ROWA + ((ch ^ (r & 7)) << 4));
+            }
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < C::TN; ++j) {
+        const int r = wx * C::WTN + j * 32 + lrow;
+#pragma unroll
+        for (int pl = 0; pl < C::QP; ++pl)
+#pragma unroll
+          for (int sidx = 0; sidx < 2; ++sidx) {
+            const int ch = (kk + 16 * h + 8 * sidx) / 8;
+            fb[pl][j][sidx] = *reinterpret_cast<const bf16x8 *>(
+                st + C::JP * C::A_BYTES + pl * C::B_BYTES + r * C::ROWB + ((ch ^ (r & 7)) << 4));
+          }
+      }
+#pragma unroll
+      for (int sidx = 0; sidx < 2; ++sidx)
+#pragma unroll
+        for (int i = 0; i < C::TM; ++i)
+#pragma unroll
+          for (int j = 0; j < C::TN; ++j)
+#pragma unroll
+            for (int pa = 0; pa < C::JP; ++pa)
+#pragma unroll
+              for (int pb = 0; pb < C::QP; ++pb)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[pa][i][sidx],
+                                                                    fb[pb][j][sidx], acc[i][j],
+                                                                    0, 0, 0);
+    }
+  }
+  wait_vm_barrier_b<0>();
+}
+
 template <int ORDER, int WALL>
 __device__ __forceinline__ void update_b(float q, float p, float f, float dt, float zeta, float k,
                                          float inv_m, float qmax, float pmax, float &qn,
@@ -253,20 +448,108 @@ __global__ __launch_bounds__(C::NT) void step_bf16_kernel(BStepArgs a) {
     }
 }
 
+template <class C, int ORDER, int WALL>
+__global__ __launch_bounds__(C::NT) void step_bf16_dma_kernel(BStepArgs a) {
+  __shared__ __attribute__((aligned(16))) uint8_t smem[C::LDS_BYTES];
+  const int m0 = blockIdx.x * C::BM, n0 = blockIdx.y * C::BN;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wy = wave / C::WN, wx = wave % C::WN;
+  // state of this lane's outputs, loaded while the contraction runs
+  floatx4 q4[C::TM][4][C::TN], p4[C::TM][4][C::TN], h4[C::TM][4];
+#pragma unroll
+  for (int i = 0; i < C::TM; ++i)
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      const int row = m0 + wy * C::WTM + i * 32 + g * 8 + (lane / 32) * 4;
+      h4[i][g] = floatx4{0.f, 0.f, 0.f, 0.f};
+      if (a.h) h4[i][g] = *reinterpret_cast<const floatx4 *>(a.h + row);
+#pragma unroll
+      for (int j = 0; j < C::TN; ++j) {
+        const size_t off = (size_t)(n0 + wx * C::WTN + j * 32 + (lane % 32)) * a.ld + row;
+        q4[i][g][j] = *reinterpret_cast<const floatx4 *>(a.q_in + off);
+        p4[i][g][j] = *reinterpret_cast<const floatx4 *>(a.p_in + off);
+      }
+    }
+  floatx16 acc[C::TM][C::TN];
+  bf16_mainloop_dma<C>(a, m0, n0, acc, smem);
+
+  const float dt = a.dt[a.t], zeta = a.zeta[a.t];
+#pragma unroll
+  for (int i = 0; i < C::TM; ++i)
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      const int row = m0 + wy * C::WTM + i * 32 + g * 8 + (lane / 32) * 4;
+#pragma unroll
+      for (int j = 0; j < C::TN; ++j) {
+        const size_t off = (size_t)(n0 + wx * C::WTN + j * 32 + (lane % 32)) * a.ld + row;
+        floatx4 qn, pn;
+        uint32_t b0[4], b1[4], b2[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          float qv, pv;
+          update_b<ORDER, WALL>(q4[i][g][j][v], p4[i][g][j][v], acc[i][j][4 * g + v] + h4[i][g][v],
+                                dt, zeta, a.k, a.inv_m, a.qmax, a.pmax, qv, pv);
+          qn[v] = qv;
+          pn[v] = pv;
+          b0[v] = bf16_bits(qv);
+          if (C::QP == 3) {
+            const float r1 = qv - bf16_to_f32(b0[v]);  // exact
+            b1[v] = bf16_bits(r1);
+            const float r2 = r1 - bf16_to_f32(b1[v]);  // exact
+            b2[v] = bf16_bits(r2);
+          }
+        }
+        *reinterpret_cast<floatx4 *>(a.q_out + off) = qn;
+        *reinterpret_cast<floatx4 *>(a.p_out + off) = pn;
+        uint16_t *qb = a.qb_out + off;
+        *reinterpret_cast<uintx2 *>(qb) = uintx2{b0[0] | (b0[1] << 16), b0[2] | (b0[3] << 16)};
+        if (C::QP == 3) {
+          *reinterpret_cast<uintx2 *>(qb + a.plane_stride) =
+              uintx2{b1[0] | (b1[1] << 16), b1[2] | (b1[3] << 16)};
+          *reinterpret_cast<uintx2 *>(qb + 2 * a.plane_stride) =
+              uintx2{b2[0] | (b2[1] << 16), b2[2] | (b2[3] << 16)};
+        }
+      }
+    }
+}
+
+template <class C>
+static hipError_t launch_bd(const BStepArgs &a, hipStream_t s) {
+  if (a.n_pad % C::BM || a.r_pad % C::BN || a.n_pad % C::BK) return hipErrorInvalidValue;
+  dim3 grid(a.n_pad / C::BM, a.r_pad / C::BN), block(C::NT);
+  switch (a.order * 2 + a.wall) {
+    case 0: step_bf16_dma_kernel<C, SI_ORDER_PAPER, SI_WALL_CLAMP><<<grid, block, 0, s>>>(a); break;
+    case 1: step_bf16_dma_kernel<C, SI_ORDER_PAPER, SI_WALL_INELASTIC><<<grid, block, 0, s>>>(a); break;
+    case 2: step_bf16_dma_kernel<C, SI_ORDER_SYMPLECTIC, SI_WALL_CLAMP><<<grid, block, 0, s>>>(a); break;
+    case 3: step_bf16_dma_kernel<C, SI_ORDER_SYMPLECTIC, SI_WALL_INELASTIC><<<grid, block, 0, s>>>(a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 // BF16 tile table: id, BM, BN, waves WM x WN, slab depth BK.
-#define SI_BF16_TILES(X)      \
-  X(1, 64, 64, 2, 2, 64)      \
-  X(2, 64, 128, 2, 2, 64)     \
-  X(3, 128, 64, 2, 2, 64)     \
-  X(4, 128, 128, 2, 2, 64)    \
-  X(5, 128, 128, 2, 4, 64)    \
-  X(6, 64, 64, 2, 2, 128)
+// Stages 0: register-staged double buffer; >= 3: direct-to-LDS ring (the
+// FP8 J form needs BK = 128 there).
+#define SI_BF16_TILES(X)         \
+  X(1, 64, 64, 2, 2, 64, 0)      \
+  X(2, 64, 128, 2, 2, 64, 0)     \
+  X(3, 128, 64, 2, 2, 64, 0)     \
+  X(4, 128, 128, 2, 2, 64, 0)    \
+  X(5, 128, 128, 2, 4, 64, 0)    \
+  X(6, 64, 64, 2, 2, 128, 0)     \
+  X(7, 64, 64, 2, 2, 64, 3)      \
+  X(8, 64, 64, 2, 2, 64, 4)      \
+  X(9, 64, 64, 2, 2, 128, 3)     \
+  X(10, 64, 128, 2, 2, 64, 3)    \
+  X(11, 128, 64, 2, 2, 64, 3)    \
+  X(12, 128, 128, 2, 2, 64, 3)   \
+  X(13, 64, 64, 2, 2, 128, 4)
 
 TileShape tile_shape_bf16(int32_t tile) {
   switch (tile) {
-#define SI_SHAPE(id, bm, bn, wm, wn, bk) \
-  case id:                               \
-    return {bm, bn, "step_bf16_" #bm "x" #bn "_w" #wm "x" #wn "_k" #bk};
+#define SI_SHAPE(id, bm, bn, wm, wn, bk, st) \
+  case id:                                   \
+    return {bm, bn, "step_bf16_" #bm "x" #bn "_w" #wm "x" #wn "_k" #bk "_s" #st};
     SI_BF16_TILES(SI_SHAPE)
 #undef SI_SHAPE
     default: return {0, 0, "invalid"};
@@ -287,12 +570,59 @@ static hipError_t launch_b(const BStepArgs &a, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <int BM, int BN, int WM, int WN, int BK, int ST, int JFMT, int QP>
+static hipError_t launch_sel(const BStepArgs &a, hipStream_t s) {
+  if constexpr (ST == 0) {
+    return launch_b<Bf16Cfg<BM, BN, WM, WN, BK, JFMT, QP>>(a, s);
+  } else if constexpr (JFMT == 1 && BK < 128) {
+    return hipErrorInvalidValue;  // FP8 rows must be 128 bytes for the swizzle
+  } else {
+    using C = Bf16DmaCfg<BM, BN, WM, WN, BK, JFMT, QP, ST>;
+    if constexpr (C::LDS_BYTES > 160 * 1024)
+      return hipErrorInvalidValue;
+    else
+      return launch_bd<C>(a, s);
+  }
+}
+
+template <int BM, int BN, int WM, int WN, int BK, int ST, int JFMT, int QP>
+static constexpr bool sel_valid() {
+  if constexpr (ST == 0)
+    return true;
+  else if constexpr (JFMT == 1 && BK < 128)
+    return false;
+  else
+    return Bf16DmaCfg<BM, BN, WM, WN, BK, JFMT, QP, ST>::LDS_BYTES <= 160 * 1024;
+}
+
+template <int JFMT, int QP>
+static bool valid_fmt(int32_t tile) {
+  switch (tile) {
+#define SI_VALID(id, bm, bn, wm, wn, bk, st) \
+  case id:                                   \
+    return sel_valid<bm, bn, wm, wn, bk, st, JFMT, QP>();
+    SI_BF16_TILES(SI_VALID)
+#undef SI_VALID
+    default: return false;
+  }
+}
+
+bool tile_valid_bf16(int32_t tile, int32_t precision) {
+  switch (precision) {
+    case SI_PREC_BF16X_BF16J: return valid_fmt<0, 1>(tile);
+    case SI_PREC_BF16X_FP8J: return valid_fmt<1, 1>(tile);
+    case SI_PREC_BF16X_HILOJ: return valid_fmt<2, 1>(tile);
+    case SI_PREC_BF16X3_EXACTJ: return valid_fmt<0, 3>(tile);
+    default: return false;
+  }
+}
+
 template <int JFMT, int QP>
 static hipError_t launch_fmt(int32_t tile, const BStepArgs &a, hipStream_t s) {
   switch (tile) {
-#define SI_LAUNCH(id, bm, bn, wm, wn, bk) \
-  case id:                                \
-    return launch_b<Bf16Cfg<bm, bn, wm, wn, bk, JFMT, QP>>(a, s);
+#define SI_LAUNCH(id, bm, bn, wm, wn, bk, st) \
+  case id:                                    \
+    return launch_sel<bm, bn, wm, wn, bk, st, JFMT, QP>(a, s);
     SI_BF16_TILES(SI_LAUNCH)
 #undef SI_LAUNCH
     default: return hipErrorInvalidValue;
