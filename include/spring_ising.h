@@ -179,6 +179,24 @@ si_status spring_ising_get_state(si_ctx *ctx, float *x, float *p, int32_t *t);
  * 0 <= t <= total_steps.  Resuming from a saved state is bit-identical. */
 si_status spring_ising_set_state(si_ctx *ctx, const float *x, const float *p, int32_t t);
 
+/* Gradient of the relaxed end-energy with respect to the step schedules
+ * (adjoint; the paper gives the forward iteration only, Eq. (8), and its
+ * walls, Eq. (6) and Methods).  From the current state at step t0 the
+ * context runs the remaining total_steps - t0 steps (ending there, as run()
+ * would) and evaluates
+ *   loss = (1/R) sum_r -1/2 q_r^T J q_r   (final positions, field excluded)
+ * and dloss/ddt[n], dloss/dzeta[n] for every step n >= t0 (entries n < t0
+ * are set to 0).  Reverse mode with checkpoints every ckpt_every steps and
+ * a recomputed forward per segment; the clamp derivative is 1 on the closed
+ * interval.  The per-step inner products are accumulated in FP64.
+ *   loss  : device, 1 double.
+ *   dL_ddt, dL_dzeta: device, total_steps doubles each.
+ * Supported for the paper order, clamping walls, FP32 precision and no
+ * field; otherwise SI_ERR_UNSUPPORTED.  Allocates its workspace on first use
+ * (about (ckpt_every + 1 + 2 (S - t0)/ckpt_every) state copies). */
+si_status spring_ising_relaxed_energy_grad(si_ctx *ctx, int32_t ckpt_every, double *loss,
+                                           double *dL_ddt, double *dL_dzeta);
+
 /* Fill *info (host). */
 si_status spring_ising_info(si_ctx *ctx, si_info *info);
 

@@ -36,6 +36,7 @@ struct StepArgs {
   float k, inv_m, qmax, pmax;
   int32_t order;      // si_order
   int32_t wall;       // si_wall
+  uint8_t *mask_out;  // nullable: per element bit 0 = |u| <= qmax, bit 1 = |v| <= pmax
 };
 
 hipError_t launch_step_f32(int32_t tile, const StepArgs &a, hipStream_t s);
@@ -80,6 +81,22 @@ hipError_t launch_energy_i8(const int8_t *J8, const int8_t *S8, const int8_t *h8
 hipError_t launch_energy_i8_finalize(int32_t *acc, int32_t r, int32_t *e_int,
                                      double *e_real, hipStream_t s);
 hipError_t launch_zero_i32(int32_t *p, int64_t count, hipStream_t s);
+
+// Adjoint of the relaxed end-energy (paper order, clamping walls, FP32).
+constexpr int ADJ_BM = 32, ADJ_BN = 32;
+hipError_t launch_adj_seed(const float *J, const float *q, float *lamq, float *lamp, double *part,
+                           int32_t n_pad, int32_t r_pad, float inv_r, hipStream_t s);
+hipError_t launch_adj_step(const float *J, const float *lamq_in, const float *lamp_in,
+                           const uint8_t *mask, const float *q_n, const float *p_n,
+                           float *lamq_out, float *lamp_out, double *part, const float *dt,
+                           const float *zeta, int32_t n, float k, float inv_m, int32_t n_pad,
+                           int32_t r_pad, hipStream_t s);
+// mode 0: loss[0] = -1/2 * sum(part[:,0]) / r_count;  mode 1: gradient entries
+// g_dt[n], g_zeta[n] from the three partial sums of step n.
+hipError_t launch_adj_reduce(const double *part, int32_t nwg, int32_t mode, double *loss,
+                             double *g_dt, double *g_zeta, const float *dt, const float *zeta,
+                             int32_t n, float k, float inv_m, int32_t r_count, hipStream_t s);
+hipError_t launch_fill_f64(double *p, int64_t count, double v, hipStream_t s);
 
 // Layout conversion and validation.
 hipError_t launch_pack_matrix(const float *src, int32_t n, float *dst, int8_t *dst8,

@@ -95,6 +95,11 @@ struct si_ctx {
   int64_t bytes = 0;
   std::vector<void *> allocs;
   std::vector<float> host_dt, host_zeta;  // kept alive for the async upload
+  // adjoint workspace
+  float *adj_ckpt = nullptr, *adj_seg = nullptr, *adj_lam = nullptr;
+  uint8_t *adj_mask = nullptr;
+  double *adj_part = nullptr;
+  int64_t adj_ckpt_cap = 0, adj_seg_cap = 0;
 
   template <class T>
   hipError_t alloc(T **ptr, int64_t count) {
@@ -415,6 +420,25 @@ static si_status do_steps_lowp(si_ctx *c, int32_t n_steps) {
   return SI_OK;
 }
 
+static StepArgs step_args(si_ctx *c) {
+  StepArgs a;
+  a.J = c->J;
+  a.dt = c->dt;
+  a.zeta = c->zeta;
+  a.h = c->has_field ? c->hf : nullptr;
+  a.ld = c->n_pad;
+  a.n_pad = c->n_pad;
+  a.r_pad = c->r_pad;
+  a.k = c->prm.k;
+  a.inv_m = 1.0f / c->prm.m;
+  a.qmax = c->prm.qmax;
+  a.pmax = c->prm.pmax;
+  a.order = c->prm.order;
+  a.wall = c->prm.wall;
+  a.mask_out = nullptr;
+  return a;
+}
+
 static si_status do_steps(si_ctx *c, int32_t n_steps) {
   if (c->qplanes) return do_steps_lowp(c, n_steps);
   StepArgs a;
@@ -437,9 +461,91 @@ static si_status do_steps(si_ctx *c, int32_t n_steps) {
     a.q_out = c->q[c->cur ^ 1];
     a.p_out = c->p[c->cur ^ 1];
     a.t = c->t;
+    a.mask_out = nullptr;
     SI_HIP(c, launch_step_f32(c->tile, a, c->stream));
     c->cur ^= 1;
     c->t += 1;
+  }
+  return SI_OK;
+}
+
+si_status spring_ising_relaxed_energy_grad(si_ctx *c, int32_t ckpt_every, double *loss,
+                                           double *g_dt, double *g_zeta) {
+  SI_USABLE(c);
+  if (ckpt_every < 1) return fail(SI_ERR_INVALID, "relaxed_energy_grad: ckpt_every < 1");
+  if (!is_device_ptr(loss) || !is_device_ptr(g_dt) || !is_device_ptr(g_zeta))
+    return fail(SI_ERR_INVALID, "relaxed_energy_grad: outputs must be device pointers");
+  if (c->prm.order != SI_ORDER_PAPER || c->prm.wall != SI_WALL_CLAMP ||
+      c->prm.precision != SI_PREC_FP32 || c->has_field)
+    return fail(SI_ERR_UNSUPPORTED, "relaxed_energy_grad: needs paper order, clamping walls, "
+                "FP32 precision and no field");
+  const int32_t S = c->prm.total_steps, t0 = c->t, C = ckpt_every;
+  const int32_t nseg = (S - t0 + C - 1) / C;
+  const int64_t NR = (int64_t)c->n_pad * c->r_pad;
+  const int32_t nwg = (c->n_pad / ADJ_BM) * (c->r_pad / ADJ_BN);
+  if ((int64_t)nseg * 2 * NR > c->adj_ckpt_cap) {
+    SI_HIP(c, c->alloc(&c->adj_ckpt, (int64_t)(nseg > 0 ? nseg : 1) * 2 * NR));
+    c->adj_ckpt_cap = (int64_t)(nseg > 0 ? nseg : 1) * 2 * NR;
+  }
+  if ((int64_t)(C + 1) * 2 * NR > c->adj_seg_cap) {
+    SI_HIP(c, c->alloc(&c->adj_seg, (int64_t)(C + 1) * 2 * NR));
+    SI_HIP(c, c->alloc(&c->adj_mask, (int64_t)C * NR));
+    c->adj_seg_cap = (int64_t)(C + 1) * 2 * NR;
+  }
+  if (!c->adj_lam) {
+    SI_HIP(c, c->alloc(&c->adj_lam, 4 * NR));
+    SI_HIP(c, c->alloc(&c->adj_part, (int64_t)nwg * 3));
+  }
+  const float inv_r = 1.0f / (float)c->r, inv_m = 1.0f / c->prm.m, k = c->prm.k;
+  SI_HIP(c, launch_fill_f64(g_dt, S, 0.0, c->stream));
+  SI_HIP(c, launch_fill_f64(g_zeta, S, 0.0, c->stream));
+
+  // forward with checkpoints at the start of every segment
+  for (int32_t sg = 0; sg < nseg; ++sg) {
+    float *ck = c->adj_ckpt + (int64_t)sg * 2 * NR;
+    SI_HIP(c, hipMemcpyAsync(ck, c->q[c->cur], NR * sizeof(float), hipMemcpyDeviceToDevice,
+                             c->stream));
+    SI_HIP(c, hipMemcpyAsync(ck + NR, c->p[c->cur], NR * sizeof(float),
+                             hipMemcpyDeviceToDevice, c->stream));
+    const int32_t len = (S - c->t) < C ? (S - c->t) : C;
+    si_status st = do_steps(c, len);
+    if (st != SI_OK) return st;
+  }
+  // seed: lq_S = -(1/R) J q_S, lp_S = 0, and the loss
+  float *lam[2][2] = {{c->adj_lam, c->adj_lam + NR}, {c->adj_lam + 2 * NR, c->adj_lam + 3 * NR}};
+  int lc = 0;
+  SI_HIP(c, launch_adj_seed(c->J, c->q[c->cur], lam[0][0], lam[0][1], c->adj_part, c->n_pad,
+                            c->r_pad, inv_r, c->stream));
+  SI_HIP(c, launch_adj_reduce(c->adj_part, nwg, 0, loss, nullptr, nullptr, c->dt, c->zeta, 0, k,
+                              inv_m, c->r, c->stream));
+  // reverse sweep, one segment at a time
+  StepArgs a = step_args(c);
+  for (int32_t sg = nseg - 1; sg >= 0; --sg) {
+    const int32_t t_a = t0 + sg * C;
+    const int32_t len = (S - t_a) < C ? (S - t_a) : C;
+    const float *ck = c->adj_ckpt + (int64_t)sg * 2 * NR;
+    float *sq = c->adj_seg;  // state j of the segment: q at sq + 2 j NR, p at + NR
+    SI_HIP(c, hipMemcpyAsync(sq, ck, 2 * NR * sizeof(float), hipMemcpyDeviceToDevice,
+                             c->stream));
+    for (int32_t j = 0; j < len; ++j) {  // recompute, recording the wall masks
+      a.q_in = sq + 2 * j * NR;
+      a.p_in = sq + 2 * j * NR + NR;
+      a.q_out = sq + 2 * (j + 1) * NR;
+      a.p_out = sq + 2 * (j + 1) * NR + NR;
+      a.mask_out = c->adj_mask + (int64_t)j * NR;
+      a.t = t_a + j;
+      SI_HIP(c, launch_step_f32(c->tile, a, c->stream));
+    }
+    for (int32_t j = len - 1; j >= 0; --j) {
+      const int32_t n = t_a + j;
+      SI_HIP(c, launch_adj_step(c->J, lam[lc][0], lam[lc][1], c->adj_mask + (int64_t)j * NR,
+                                sq + 2 * j * NR, sq + 2 * j * NR + NR, lam[lc ^ 1][0],
+                                lam[lc ^ 1][1], c->adj_part, c->dt, c->zeta, n, k, inv_m,
+                                c->n_pad, c->r_pad, c->stream));
+      SI_HIP(c, launch_adj_reduce(c->adj_part, nwg, 1, nullptr, g_dt, g_zeta, c->dt, c->zeta, n,
+                                  k, inv_m, c->r, c->stream));
+      lc ^= 1;
+    }
   }
   return SI_OK;
 }

@@ -85,6 +85,7 @@ _SIGNATURES = {
     "spring_ising_get_state": [_P, _P, _P, ctypes.POINTER(_I)],
     "spring_ising_set_state": [_P, _P, _P, _I],
     "spring_ising_info": [_P, ctypes.POINTER(si_info)],
+    "spring_ising_relaxed_energy_grad": [_P, _I, _P, _P, _P],
     "spring_ising_destroy": [_P],
 }
 
@@ -213,6 +214,13 @@ def spring_ising_set_state(ctx, x, p=None, t=0):
                                                  _ptr(p, torch.float32, name="p"), int(t)))
 
 
+def spring_ising_relaxed_energy_grad(ctx, ckpt_every, loss, dl_ddt, dl_dzeta):
+    import torch
+    _check(load_library().spring_ising_relaxed_energy_grad(
+        ctx, int(ckpt_every), _ptr(loss, torch.float64, 1, "loss"),
+        _ptr(dl_ddt, torch.float64, name="dL_ddt"), _ptr(dl_dzeta, torch.float64, name="dL_dzeta")))
+
+
 def spring_ising_info(ctx) -> dict:
     info = si_info()
     _check(load_library().spring_ising_info(ctx, ctypes.byref(info)))
@@ -311,3 +319,13 @@ class SpringIsing:
 
     def info(self):
         return spring_ising_info(self.ctx)
+
+    def relaxed_energy_grad(self, ckpt_every=100):
+        """Run the remaining steps; return (loss, dL/ddt, dL/dzeta) as float64
+        CUDA tensors (see spring_ising_relaxed_energy_grad)."""
+        import torch
+        loss = torch.empty(1, dtype=torch.float64, device=self.device)
+        g_dt = torch.empty(self.total_steps, dtype=torch.float64, device=self.device)
+        g_z = torch.empty_like(g_dt)
+        spring_ising_relaxed_energy_grad(self.ctx, ckpt_every, loss, g_dt, g_z)
+        return loss, g_dt, g_z

@@ -1,0 +1,158 @@
+"""Adjoint (gradient of the relaxed end-energy w.r.t. the Delta and zeta
+schedules) through the C ABI, against the FP64 oracle adjoint, exact dual
+numbers and invariants."""
+import math
+from fractions import Fraction as Fr
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2305_07187_amd import instances
+
+from closed_forms import scalar_loss_derivative
+from gpu_common import DT, QMAX, ZE, ZS, F32, announce, ensure_built, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def _grad(J, x0, dt, zeta, ckpt=100, **kw):
+    import torch
+    si = ensure_built()
+    m = si.SpringIsing(to_dev(J), to_dev(x0), total_steps=len(dt), **kw)
+    m.set_schedule(to_dev(np.asarray(dt, np.float32)), to_dev(np.asarray(zeta, np.float32)))
+    loss, gd, gz = m.relaxed_energy_grad(ckpt)
+    torch.cuda.synchronize()
+    t = m.info()["t"]
+    m.close()
+    assert t == len(dt)
+    return float(loss.cpu()[0]), gd.cpu().numpy(), gz.cpu().numpy()
+
+
+def _sched(S_total, S):
+    return (oracle.dt_schedule(S_total, DT)[:S], oracle.zeta_schedule(S_total, ZS, ZE)[:S])
+
+
+def _rel(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def test_adjoint_vs_oracle_small():
+    n, r, S = 100, 8, 100
+    announce(f"adjoint vs oracle N={n} R={r} S={S}")
+    J = instances.make_pm1(n, 0)
+    x0 = instances.make_x0(n, r, 0)
+    dt, zeta = _sched(1000, S)
+    L, gd, gz = _grad(J, x0, dt, zeta, ckpt=30)
+    Lo, gdo, gzo = oracle.relaxed_energy_grad(J.astype(np.float64), x0.T.astype(np.float64), None,
+                                              dt.astype(np.float64), zeta.astype(np.float64),
+                                              qmax=QMAX)
+    announce(f"  loss {L:.8e} vs {Lo:.8e}; grad rel err dt {_rel(gd, gdo):.2e} "
+             f"zeta {_rel(gz, gzo):.2e}")
+    assert abs(L - Lo) <= 1e-5 * abs(Lo)
+    assert _rel(gd, gdo) <= 1e-4 and _rel(gz, gzo) <= 1e-4
+
+
+@pytest.mark.parametrize("which", ["dt", "zeta"])
+def test_adjoint_exact_dual_numbers(which):
+    # uniform coupling a = 1, every spin at c: N times the exact derivative of
+    # the scalar recurrence (walls reached during the run)
+    n, S = 8, 56
+    announce(f"adjoint exact dual numbers ({which})")
+    J = (np.ones((n, n)) - np.eye(n)).astype(np.float32)
+    c = 0.25
+    x0 = np.full((1, n), c, np.float32)
+    dt = [0.125] * S
+    zeta = [0.05 + 0.00390625 * i for i in range(S)]
+    L, gd, gz = _grad(J, x0, dt, zeta, ckpt=9)
+    g = gd if which == "dt" else gz
+    for nv in (0, 7, S // 2, S - 1):
+        val, der = scalar_loss_derivative(Fr(c), Fr(n - 1), dt, zeta, Fr(1, 2), Fr(1), Fr(QMAX),
+                                          Fr(2), nv, which)
+        assert L == pytest.approx(float(val) * n, rel=1e-5)
+        assert g[nv] == pytest.approx(float(der) * n, rel=2e-4, abs=1e-4 * abs(float(der) * n) + 1e-6)
+
+
+def test_adjoint_invariants():
+    n, r, S = 300, 32, 120
+    announce("adjoint determinism, checkpoint interval, gauge")
+    J = instances.make_pm1(n, 3)
+    x0 = instances.make_x0(n, r, 3)
+    dt, zeta = _sched(1000, S)
+    a = _grad(J, x0, dt, zeta, ckpt=100)
+    b = _grad(J, x0, dt, zeta, ckpt=100)
+    c = _grad(J, x0, dt, zeta, ckpt=7)
+    d1 = _grad(J, x0, dt, zeta, ckpt=1)
+    for other in (b, c, d1):
+        assert other[0] == a[0]
+        assert np.array_equal(other[1], a[1]) and np.array_equal(other[2], a[2])
+    d = np.where(np.random.default_rng(0).random(n) < 0.5, -1.0, 1.0).astype(np.float32)
+    g = _grad((d[:, None] * J * d[None, :]).astype(np.float32), x0 * d[None, :], dt, zeta, ckpt=13)
+    assert g[0] == a[0] and np.array_equal(g[1], a[1]) and np.array_equal(g[2], a[2])
+
+
+def test_adjoint_full_size_first_steps():
+    # N=2000, R=64 (the differentiation workload's shape), first 40 steps of
+    # its 2000-step schedule, against the FP64 oracle adjoint.
+    n, r, S = 2000, 64, 40
+    announce(f"adjoint full size N={n} R={r} first {S} steps")
+    J = instances.make_pm1(n, 0)
+    x0 = instances.make_x0(n, r, 0)
+    dt, zeta = _sched(2000, S)
+    L, gd, gz = _grad(J, x0, dt, zeta, ckpt=10)
+    Lo, gdo, gzo = oracle.relaxed_energy_grad(J.astype(np.float64), x0.T.astype(np.float64), None,
+                                              dt.astype(np.float64), zeta.astype(np.float64),
+                                              qmax=QMAX)
+    announce(f"  loss {L:.8e} vs {Lo:.8e}; grad rel err dt {_rel(gd, gdo):.2e} "
+             f"zeta {_rel(gz, gzo):.2e}")
+    assert abs(L - Lo) <= 1e-5 * abs(Lo)
+    assert _rel(gd, gdo) <= 1e-3 and _rel(gz, gzo) <= 1e-3
+
+
+def test_adjoint_full_workload_runs():
+    # the full differentiation workload: N=2000, R=64, 2000 steps, checkpoints
+    # every 100; deterministic and invariant to the checkpoint interval
+    import time
+    n, r, S = 2000, 64, 2000
+    announce(f"adjoint full workload N={n} R={r} S={S}")
+    J = instances.make_pm1(n, 0)
+    x0 = instances.make_x0(n, r, 0)
+    dt, zeta = _sched(S, S)
+    t0 = time.perf_counter()
+    a = _grad(J, x0, dt, zeta, ckpt=100)
+    el = time.perf_counter() - t0
+    b = _grad(J, x0, dt, zeta, ckpt=250)
+    assert np.all(np.isfinite(a[1])) and np.all(np.isfinite(a[2]))
+    assert a[0] == b[0] and np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
+    announce(f"  loss {a[0]:.6e}, |g_dt|max {np.abs(a[1]).max():.3e}, wall {el:.2f} s")
+
+
+def test_autograd_function():
+    import torch
+    from paper_2305_07187_amd.autograd import SpringIsingRelaxedEnergy
+    announce("autograd Function")
+    n, r, S = 100, 8, 60
+    J = instances.make_pm1(n, 1)
+    x0 = instances.make_x0(n, r, 1)
+    dt_np, z_np = _sched(1000, S)
+    dt = to_dev(dt_np).requires_grad_(True)
+    z = to_dev(z_np).requires_grad_(True)
+    loss = SpringIsingRelaxedEnergy.apply(to_dev(J), to_dev(x0), None, dt, z, 20)
+    (2.0 * loss).backward()
+    L, gd, gz = _grad(J, x0, dt_np, z_np, ckpt=20)
+    assert float(loss) == L
+    np.testing.assert_allclose(dt.grad.cpu().numpy(), (2.0 * gd).astype(np.float32), rtol=1e-6)
+    np.testing.assert_allclose(z.grad.cpu().numpy(), (2.0 * gz).astype(np.float32), rtol=1e-6)
+
+
+def test_adjoint_unsupported_configurations():
+    si = ensure_built()
+    n, r = 64, 4
+    J = to_dev(instances.make_pm1(n, 0))
+    x0 = to_dev(instances.make_x0(n, r, 0))
+    for kw in ({"order": "symplectic"}, {"wall": "inelastic"}, {"precision": "bf16x_bf16j"}):
+        m = si.SpringIsing(J, x0, total_steps=10, **kw)
+        with pytest.raises(si.SpringIsingError) as e:
+            m.relaxed_energy_grad(5)
+        assert e.value.status == si.SI_ERR_UNSUPPORTED
+        m.close()
