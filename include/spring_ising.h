@@ -142,6 +142,23 @@ si_status spring_ising_init(si_ctx **out, int32_t n, int32_t r, const float *J,
                             const float *x0, const float *p0, const si_params *prm,
                             void *hip_stream);
 
+/* Batched form: n_inst independent instances of uneven size stepped together
+ * (one grouped launch per step covers every instance), sharing r, the
+ * parameters and the schedules.
+ *   n : host, n_inst sizes (1 .. 65536).
+ *   J : host array of n_inst device pointers, instance i an n[i]*n[i]
+ *       symmetric zero-diagonal matrix.
+ *   x0: host array of n_inst device pointers, instance i r*n[i] floats;
+ *       initial momenta are 0.
+ * FP32 only (other precisions: SI_ERR_UNSUPPORTED).  In every later call the
+ * instances are concatenated: state/spin arrays hold instance i's r*n[i]
+ * values (replica-major) at offset r * (n[0] + ... + n[i-1]); energies hold
+ * instance i's r values at offset r*i.  set_field and
+ * relaxed_energy_grad are not available for a batch.  Synchronises once. */
+si_status spring_ising_init_batch(si_ctx **out, int32_t n_inst, const int32_t *n, int32_t r,
+                                  const float *const *J, const float *const *x0,
+                                  const si_params *prm, void *hip_stream);
+
 /* Replace the per-step schedules (device, total_steps floats each).
  * Delta_n must be > 0; values are not checked on the host. */
 si_status spring_ising_set_schedule(si_ctx *ctx, const float *dt, const float *zeta);

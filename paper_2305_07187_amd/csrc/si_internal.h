@@ -41,6 +41,16 @@ struct StepArgs {
 
 hipError_t launch_step_f32(int32_t tile, const StepArgs &a, hipStream_t s);
 
+// Batched form: per-instance buffers and the work list of one grouped launch.
+constexpr int BATCH_BM = 64, BATCH_BN = 64;
+struct BatchDesc {
+  const float *J;         // [n_pad][n_pad]
+  float *q0, *q1, *p0, *p1;  // [r_pad][n_pad] ping-pong state
+  int32_t n_pad, pad_;
+};
+hipError_t launch_step_batch_f32(const StepArgs &a, const BatchDesc *descs, const int4 *items,
+                                 int32_t n_items, int32_t cur, hipStream_t s);
+
 // Step on the BF16 matrix cores (precision forms).
 constexpr int32_t TILE_BF16_LAST = 13;
 TileShape tile_shape_bf16(int32_t tile);

@@ -8,6 +8,7 @@
 
 #include <new>
 #include <string>
+#include <algorithm>
 #include <vector>
 
 #include "si_internal.h"
@@ -95,6 +96,18 @@ struct si_ctx {
   int64_t bytes = 0;
   std::vector<void *> allocs;
   std::vector<float> host_dt, host_zeta;  // kept alive for the async upload
+  // batched form (n_inst > 0): per-instance buffers inside shared allocations
+  int32_t n_inst = 0;
+  std::vector<int32_t> b_n, b_npad, b_jmax;
+  std::vector<int64_t> b_xoff;            // offset of instance i in caller layouts (floats)
+  std::vector<float *> b_J, b_q[2], b_p[2];
+  std::vector<int8_t *> b_J8;             // nullptr for non-integer instances
+  std::vector<BatchDesc> b_desc_host;
+  std::vector<int4> b_items_host;
+  BatchDesc *b_desc = nullptr;
+  int4 *b_items = nullptr;
+  int32_t b_max_npad = 0;
+  int64_t b_total_n = 0;
   // adjoint workspace
   float *adj_ckpt = nullptr, *adj_seg = nullptr, *adj_lam = nullptr;
   uint8_t *adj_mask = nullptr;
@@ -344,6 +357,138 @@ si_status spring_ising_init(si_ctx **out, int32_t n, int32_t r, const float *J, 
   return SI_OK;
 }
 
+si_status spring_ising_init_batch(si_ctx **out, int32_t n_inst, const int32_t *n, int32_t r,
+                                  const float *const *J, const float *const *x0,
+                                  const si_params *prm, void *hip_stream) {
+  if (!out) return fail(SI_ERR_INVALID, "init_batch: out is null");
+  *out = nullptr;
+  if (n_inst < 1 || r < 1 || !n || !J || !x0)
+    return fail(SI_ERR_INVALID, "init_batch: n_inst, r >= 1 and n, J, x0 arrays are required");
+  if (r > (1 << 20)) return fail(SI_ERR_INVALID, "init_batch: r=%d too large", r);
+  si_status st = check_params(prm);
+  if (st != SI_OK) return st;
+  if (prm->precision != SI_PREC_FP32)
+    return fail(SI_ERR_UNSUPPORTED, "init_batch: the batched form runs in FP32");
+  for (int32_t i = 0; i < n_inst; ++i) {
+    if (n[i] < 1 || n[i] > 65536) return fail(SI_ERR_INVALID, "init_batch: n[%d]=%d", i, n[i]);
+    if (!is_device_ptr(J[i]) || !is_device_ptr(x0[i]))
+      return fail(SI_ERR_INVALID, "init_batch: J[%d], x0[%d] must be device pointers", i, i);
+  }
+  si_ctx *c = new (std::nothrow) si_ctx();
+  if (!c) return fail(SI_ERR_OOM, "init_batch: host allocation failed");
+  c->prm = *prm;
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  c->n_inst = n_inst;
+  c->r = r;
+  c->r_pad = (int32_t)round_up(r, BATCH_BN);
+  c->tile = 0;
+#define BINIT_HIP(expr)                                                                  \
+  do {                                                                                   \
+    hipError_t _e = (expr);                                                              \
+    if (_e != hipSuccess) {                                                              \
+      delete c;                                                                          \
+      return fail(_e == hipErrorOutOfMemory ? SI_ERR_OOM : SI_ERR_HIP, "init_batch: %s (%s)", \
+                  hipGetErrorString(_e), #expr);                                         \
+    }                                                                                    \
+  } while (0)
+  BINIT_HIP(hipGetDevice(&c->device));
+  BINIT_HIP(hipDeviceGetAttribute(&c->num_cus, hipDeviceAttributeMultiprocessorCount, c->device));
+  // validation of every J: one host round trip for the whole batch
+  int32_t *flags = nullptr;
+  BINIT_HIP(c->alloc(&flags, (int64_t)8 * n_inst));
+  BINIT_HIP(launch_zero_i32(flags, (int64_t)8 * n_inst, c->stream));
+  for (int32_t i = 0; i < n_inst; ++i) BINIT_HIP(launch_validate(J[i], n[i], flags + 8 * i, c->stream));
+  std::vector<int32_t> hfl((size_t)8 * n_inst);
+  BINIT_HIP(hipMemcpyAsync(hfl.data(), flags, hfl.size() * sizeof(int32_t), hipMemcpyDeviceToHost,
+                           c->stream));
+  BINIT_HIP(hipStreamSynchronize(c->stream));
+  int64_t jtot = 0, j8tot = 0, stot = 0, xoff = 0;
+  c->b_n.resize(n_inst);
+  c->b_npad.resize(n_inst);
+  c->b_jmax.resize(n_inst);
+  c->b_xoff.resize(n_inst);
+  for (int32_t i = 0; i < n_inst; ++i) {
+    const int32_t *f = &hfl[(size_t)8 * i];
+    if (f[0] || f[1] || f[2]) {
+      delete c;
+      return fail(SI_ERR_INVALID, "init_batch: J[%d] must be finite, symmetric, zero diagonal", i);
+    }
+    c->b_n[i] = n[i];
+    c->b_npad[i] = (int32_t)round_up(n[i], BATCH_BM);
+    c->b_jmax[i] = f[3] == 0 ? f[6] : -1;  // -1: not integer
+    c->b_xoff[i] = xoff;
+    xoff += (int64_t)r * n[i];
+    jtot += (int64_t)c->b_npad[i] * c->b_npad[i];
+    if (f[3] == 0) j8tot += (int64_t)c->b_npad[i] * c->b_npad[i];
+    stot += (int64_t)c->r_pad * c->b_npad[i];
+    c->b_max_npad = c->b_npad[i] > c->b_max_npad ? c->b_npad[i] : c->b_max_npad;
+    c->b_total_n += n[i];
+  }
+  c->n = (int32_t)(c->b_total_n > 0x7fffffff ? 0x7fffffff : c->b_total_n);
+  c->n_pad = c->b_max_npad;
+  float *Jall = nullptr, *sbuf[4] = {nullptr, nullptr, nullptr, nullptr};
+  int8_t *J8all = nullptr;
+  BINIT_HIP(c->alloc(&Jall, jtot));
+  if (j8tot) BINIT_HIP(c->alloc(&J8all, j8tot));
+  for (int b = 0; b < 4; ++b) BINIT_HIP(c->alloc(&sbuf[b], stot));
+  BINIT_HIP(c->alloc(&c->dt, prm->total_steps));
+  BINIT_HIP(c->alloc(&c->zeta, prm->total_steps));
+  BINIT_HIP(c->alloc(&c->S8, (int64_t)c->b_max_npad * c->r_pad));
+  BINIT_HIP(c->alloc(&c->eacc, c->r_pad));
+  BINIT_HIP(c->alloc(&c->epart, (int64_t)(c->b_max_npad / 64) * c->r_pad));
+  BINIT_HIP(launch_zero_i32(c->eacc, c->r_pad, c->stream));
+  int64_t jo = 0, j8o = 0, so = 0;
+  c->b_J.resize(n_inst);
+  c->b_J8.resize(n_inst);
+  for (int b = 0; b < 2; ++b) {
+    c->b_q[b].resize(n_inst);
+    c->b_p[b].resize(n_inst);
+  }
+  c->b_desc_host.resize(n_inst);
+  for (int32_t i = 0; i < n_inst; ++i) {
+    const int64_t nn = (int64_t)c->b_npad[i] * c->b_npad[i];
+    c->b_J[i] = Jall + jo;
+    c->b_J8[i] = c->b_jmax[i] >= 0 ? J8all + j8o : nullptr;
+    jo += nn;
+    if (c->b_jmax[i] >= 0) j8o += nn;
+    c->b_q[0][i] = sbuf[0] + so;
+    c->b_q[1][i] = sbuf[1] + so;
+    c->b_p[0][i] = sbuf[2] + so;
+    c->b_p[1][i] = sbuf[3] + so;
+    so += (int64_t)c->r_pad * c->b_npad[i];
+    BINIT_HIP(launch_pack_matrix(J[i], n[i], c->b_J[i], c->b_J8[i], c->b_npad[i], c->stream));
+    BINIT_HIP(launch_pack_state(x0[i], n[i], r, c->b_q[0][i], c->b_npad[i], c->r_pad, c->stream));
+    BINIT_HIP(launch_pack_state(nullptr, n[i], r, c->b_p[0][i], c->b_npad[i], c->r_pad, c->stream));
+    c->b_desc_host[i] = BatchDesc{c->b_J[i], c->b_q[0][i], c->b_q[1][i], c->b_p[0][i], c->b_p[1][i],
+                                  c->b_npad[i], 0};
+  }
+  // work list, longest contraction first
+  std::vector<int32_t> order(n_inst);
+  for (int32_t i = 0; i < n_inst; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int32_t x, int32_t y) { return c->b_npad[x] > c->b_npad[y]; });
+  for (int32_t i : order)
+    for (int32_t rt = 0; rt < c->b_npad[i] / BATCH_BM; ++rt)
+      for (int32_t ct = 0; ct < c->r_pad / BATCH_BN; ++ct) c->b_items_host.push_back(int4{i, rt, ct, 0});
+  BINIT_HIP(c->alloc(&c->b_desc, n_inst));
+  BINIT_HIP(c->alloc(&c->b_items, (int64_t)c->b_items_host.size()));
+  BINIT_HIP(hipMemcpyAsync(c->b_desc, c->b_desc_host.data(), sizeof(BatchDesc) * n_inst,
+                           hipMemcpyHostToDevice, c->stream));
+  BINIT_HIP(hipMemcpyAsync(c->b_items, c->b_items_host.data(),
+                           sizeof(int4) * c->b_items_host.size(), hipMemcpyHostToDevice, c->stream));
+  build_schedules(*prm, c->host_dt, c->host_zeta);
+  BINIT_HIP(hipMemcpyAsync(c->dt, c->host_dt.data(), sizeof(float) * prm->total_steps,
+                           hipMemcpyHostToDevice, c->stream));
+  BINIT_HIP(hipMemcpyAsync(c->zeta, c->host_zeta.data(), sizeof(float) * prm->total_steps,
+                           hipMemcpyHostToDevice, c->stream));
+  BINIT_HIP(hipStreamSynchronize(c->stream));  // host tables may go out of scope
+#undef BINIT_HIP
+  c->cur = 0;
+  c->t = 0;
+  *out = c;
+  return SI_OK;
+}
+
 si_status spring_ising_set_schedule(si_ctx *c, const float *dt, const float *zeta) {
   SI_USABLE(c);
   if (!is_device_ptr(dt) || !is_device_ptr(zeta))
@@ -371,6 +516,7 @@ si_status spring_ising_set_field(si_ctx *c, const float *h) {
     return SI_OK;
   }
   if (!is_device_ptr(h)) return fail(SI_ERR_INVALID, "set_field: h must be a device pointer");
+  if (c->n_inst) return fail(SI_ERR_UNSUPPORTED, "set_field: not available for a batch");
   if (!c->hf) {
     SI_HIP(c, c->alloc(&c->hf, c->n_pad));
     SI_HIP(c, c->alloc(&c->h8, c->n_pad));
@@ -439,7 +585,20 @@ static StepArgs step_args(si_ctx *c) {
   return a;
 }
 
+static si_status do_steps_batch(si_ctx *c, int32_t n_steps) {
+  StepArgs a = step_args(c);
+  for (int32_t s = 0; s < n_steps; ++s) {
+    a.t = c->t;
+    SI_HIP(c, launch_step_batch_f32(a, c->b_desc, c->b_items, (int32_t)c->b_items_host.size(),
+                                    c->cur, c->stream));
+    c->cur ^= 1;
+    c->t += 1;
+  }
+  return SI_OK;
+}
+
 static si_status do_steps(si_ctx *c, int32_t n_steps) {
+  if (c->n_inst) return do_steps_batch(c, n_steps);
   if (c->qplanes) return do_steps_lowp(c, n_steps);
   StepArgs a;
   a.J = c->J;
@@ -476,7 +635,7 @@ si_status spring_ising_relaxed_energy_grad(si_ctx *c, int32_t ckpt_every, double
   if (!is_device_ptr(loss) || !is_device_ptr(g_dt) || !is_device_ptr(g_zeta))
     return fail(SI_ERR_INVALID, "relaxed_energy_grad: outputs must be device pointers");
   if (c->prm.order != SI_ORDER_PAPER || c->prm.wall != SI_WALL_CLAMP ||
-      c->prm.precision != SI_PREC_FP32 || c->has_field)
+      c->prm.precision != SI_PREC_FP32 || c->has_field || c->n_inst)
     return fail(SI_ERR_UNSUPPORTED, "relaxed_energy_grad: needs paper order, clamping walls, "
                 "FP32 precision and no field");
   const int32_t S = c->prm.total_steps, t0 = c->t, C = ckpt_every;
@@ -566,9 +725,70 @@ si_status spring_ising_run(si_ctx *c, int32_t n_steps) {
   return do_steps(c, n_steps);
 }
 
+
+// ---- batched-context variants (instances concatenated in caller layouts) ----
+static si_status batch_spins(si_ctx *c, int8_t *s) {
+  for (int32_t i = 0; i < c->n_inst; ++i) {
+    SI_HIP(c, launch_sign(c->b_q[c->cur][i], c->S8, c->b_npad[i], c->r_pad, c->stream));
+    SI_HIP(c, launch_unpack_spins(c->S8, c->b_n[i], c->r, s + c->b_xoff[i], c->b_npad[i],
+                                  c->stream));
+  }
+  return SI_OK;
+}
+
+static si_status batch_energy(si_ctx *c, int32_t *e_int, double *e_real) {
+  std::vector<char> exact(c->n_inst);
+  for (int32_t i = 0; i < c->n_inst; ++i) {
+    const int64_t bound = (int64_t)c->b_n[i] * c->b_n[i] * (c->b_jmax[i] < 0 ? 0 : c->b_jmax[i]);
+    exact[i] = c->b_J8[i] != nullptr && bound < (1LL << 31);
+    if (e_int && !exact[i])
+      return fail(SI_ERR_UNSUPPORTED, "energy: instance %d has non-integer couplings", i);
+  }
+  for (int32_t i = 0; i < c->n_inst; ++i) {
+    int32_t *ei = e_int ? e_int + (int64_t)i * c->r : nullptr;
+    double *er = e_real ? e_real + (int64_t)i * c->r : nullptr;
+    const float *q = c->b_q[c->cur][i];
+    if (exact[i]) {
+      SI_HIP(c, launch_sign(q, c->S8, c->b_npad[i], c->r_pad, c->stream));
+      SI_HIP(c, launch_energy_i8(c->b_J8[i], c->S8, nullptr, c->eacc, c->b_npad[i], c->r_pad,
+                                 c->stream));
+      SI_HIP(c, launch_energy_i8_finalize(c->eacc, c->r, ei, er, c->stream));
+    } else if (er) {
+      SI_HIP(c, launch_energy_f32_partial(c->b_J[i], q, nullptr, c->epart, c->b_npad[i], c->r_pad,
+                                          c->stream));
+      SI_HIP(c, launch_energy_f32_finalize(c->epart, c->b_npad[i] / 64, c->r, c->r_pad, er,
+                                           c->stream));
+    }
+  }
+  return SI_OK;
+}
+
+static si_status batch_get_state(si_ctx *c, float *x, float *p) {
+  for (int32_t i = 0; i < c->n_inst; ++i) {
+    if (x)
+      SI_HIP(c, launch_unpack_state(c->b_q[c->cur][i], c->b_n[i], c->r, x + c->b_xoff[i],
+                                    c->b_npad[i], c->stream));
+    if (p)
+      SI_HIP(c, launch_unpack_state(c->b_p[c->cur][i], c->b_n[i], c->r, p + c->b_xoff[i],
+                                    c->b_npad[i], c->stream));
+  }
+  return SI_OK;
+}
+
+static si_status batch_set_state(si_ctx *c, const float *x, const float *p) {
+  for (int32_t i = 0; i < c->n_inst; ++i) {
+    SI_HIP(c, launch_pack_state(x + c->b_xoff[i], c->b_n[i], c->r, c->b_q[c->cur][i], c->b_npad[i],
+                                c->r_pad, c->stream));
+    SI_HIP(c, launch_pack_state(p ? p + c->b_xoff[i] : nullptr, c->b_n[i], c->r,
+                                c->b_p[c->cur][i], c->b_npad[i], c->r_pad, c->stream));
+  }
+  return SI_OK;
+}
+
 si_status spring_ising_spins(si_ctx *c, int8_t *s) {
   SI_USABLE(c);
   if (!is_device_ptr(s)) return fail(SI_ERR_INVALID, "spins: s must be a device pointer");
+  if (c->n_inst) return batch_spins(c, s);
   SI_HIP(c, launch_sign(c->q[c->cur], c->S8, c->n_pad, c->r_pad, c->stream));
   SI_HIP(c, launch_unpack_spins(c->S8, c->n, c->r, s, c->n_pad, c->stream));
   return SI_OK;
@@ -579,6 +799,7 @@ si_status spring_ising_energy(si_ctx *c, int32_t *e_int, double *e_real) {
   if ((e_int && !is_device_ptr(e_int)) || (e_real && !is_device_ptr(e_real)))
     return fail(SI_ERR_INVALID, "energy: outputs must be device pointers");
   if (!e_int && !e_real) return SI_OK;
+  if (c->n_inst) return batch_energy(c, e_int, e_real);
   // exact int32 path: integer J (and field) with a sum that cannot overflow
   const int64_t jmax = c->hflags[6];
   const int64_t bound = (int64_t)c->n * c->n * jmax +
@@ -606,6 +827,10 @@ si_status spring_ising_get_state(si_ctx *c, float *x, float *p, int32_t *t) {
   SI_USABLE(c);
   if ((x && !is_device_ptr(x)) || (p && !is_device_ptr(p)))
     return fail(SI_ERR_INVALID, "get_state: x and p must be device pointers");
+  if (c->n_inst) {
+    if (t) *t = c->t;
+    return batch_get_state(c, x, p);
+  }
   if (x) SI_HIP(c, launch_unpack_state(c->q[c->cur], c->n, c->r, x, c->n_pad, c->stream));
   if (p) SI_HIP(c, launch_unpack_state(c->p[c->cur], c->n, c->r, p, c->n_pad, c->stream));
   if (t) *t = c->t;
@@ -619,6 +844,11 @@ si_status spring_ising_set_state(si_ctx *c, const float *x, const float *p, int3
     return fail(SI_ERR_INVALID, "set_state: x and p must be device pointers");
   if (t < 0 || t > c->prm.total_steps)
     return fail(SI_ERR_RANGE, "set_state: t=%d outside [0, %d]", t, c->prm.total_steps);
+  if (c->n_inst) {
+    si_status st = batch_set_state(c, x, p);
+    if (st == SI_OK) c->t = t;
+    return st;
+  }
   SI_HIP(c, launch_pack_state(x, c->n, c->r, c->q[c->cur], c->n_pad, c->r_pad, c->stream));
   SI_HIP(c, launch_pack_state(p, c->n, c->r, c->p[c->cur], c->n_pad, c->r_pad, c->stream));
   if (c->qplanes)
@@ -638,14 +868,23 @@ si_status spring_ising_info(si_ctx *c, si_info *info) {
   info->t = c->t;
   info->total_steps = c->prm.total_steps;
   info->j_integer = c->J8 != nullptr;
+  if (c->n_inst) {
+    info->j_integer = 1;
+    for (int32_t i = 0; i < c->n_inst; ++i)
+      if (!c->b_J8[i]) info->j_integer = 0;
+  }
   info->j_fp8_exact = c->hflags[4] == 0;
   info->j_bf16_exact = c->hflags[5] == 0;
   info->tile = c->tile;
   info->precision = c->prm.precision;
   info->graph_steps = 0;
   info->device_bytes = c->bytes;
-  snprintf(info->kernel_name, sizeof info->kernel_name, "%s",
-           shape_of(c->prm.precision, c->tile).name);
+  if (c->n_inst)
+    snprintf(info->kernel_name, sizeof info->kernel_name, "step_batch_f32_%dx%d_x%d", BATCH_BM,
+             BATCH_BN, c->n_inst);
+  else
+    snprintf(info->kernel_name, sizeof info->kernel_name, "%s",
+             shape_of(c->prm.precision, c->tile).name);
   return SI_OK;
 }
 

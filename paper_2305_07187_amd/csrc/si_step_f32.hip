@@ -44,11 +44,15 @@ __device__ __forceinline__ void update(float q, float p, float f, float dt, floa
   if (WALL == SI_WALL_INELASTIC && fabsf(u) > qmax) pn = 0.f;
 }
 
+// One BM x BN output tile of one step: contraction over k in [0, K) of the
+// rows m0.. of J (leading dimension ld) with the replicas n0.. of q_in, then
+// the update.  Shared by the single-instance and the batched kernels.
 template <class C, int ORDER, int WALL>
-__global__ __launch_bounds__(C::NT) void step_f32_kernel(StepArgs a) {
-  __shared__ __attribute__((aligned(16))) float smem[C::LDS_FLOATS];
-  const int m0 = blockIdx.x * C::BM;
-  const int n0 = blockIdx.y * C::BN;
+__device__ __forceinline__ void step_tile(const StepArgs &a, const float *__restrict__ Jm,
+                                          const float *__restrict__ q_in,
+                                          const float *__restrict__ p_in, float *__restrict__ q_out,
+                                          float *__restrict__ p_out, int ld, int m0, int n0,
+                                          float *smem) {
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int wy = wave / C::WN, wx = wave % C::WN;
@@ -66,17 +70,17 @@ __global__ __launch_bounds__(C::NT) void step_f32_kernel(StepArgs a) {
 #pragma unroll
       for (int j = 0; j < C::TN; ++j) {
         const int col = n0 + wx * C::WTN + j * C::MB + (lane % C::MB);
-        const size_t off = (size_t)col * a.ld + row;
-        q4[i][g][j] = *reinterpret_cast<const floatx4 *>(a.q_in + off);
-        p4[i][g][j] = *reinterpret_cast<const floatx4 *>(a.p_in + off);
+        const size_t off = (size_t)col * ld + row;
+        q4[i][g][j] = *reinterpret_cast<const floatx4 *>(q_in + off);
+        p4[i][g][j] = *reinterpret_cast<const floatx4 *>(p_in + off);
       }
     }
 
   typename C::acc_t acc[C::TM][C::TN];
   if constexpr (C::STAGES > 0)
-    f32_mainloop_dma<C>(a.J, a.q_in, a.ld, a.n_pad, m0, n0, acc, smem);
+    f32_mainloop_dma<C>(Jm, q_in, ld, ld, m0, n0, acc, smem);
   else
-    f32_mainloop<C, B_PLAIN>(a.J, a.q_in, a.ld, a.n_pad, m0, n0, acc, smem);
+    f32_mainloop<C, B_PLAIN>(Jm, q_in, ld, ld, m0, n0, acc, smem);
 
   const float dt = a.dt[a.t], zeta = a.zeta[a.t];
 #pragma unroll
@@ -87,7 +91,7 @@ __global__ __launch_bounds__(C::NT) void step_f32_kernel(StepArgs a) {
 #pragma unroll
       for (int j = 0; j < C::TN; ++j) {
         const int col = n0 + wx * C::WTN + j * C::MB + (lane % C::MB);
-        const size_t off = (size_t)col * a.ld + row;
+        const size_t off = (size_t)col * ld + row;
         floatx4 qn, pn;
         uint32_t mk = 0;
 #pragma unroll
@@ -107,12 +111,34 @@ __global__ __launch_bounds__(C::NT) void step_f32_kernel(StepArgs a) {
             mk |= bits << (8 * v);
           }
         }
-        *reinterpret_cast<floatx4 *>(a.q_out + off) = qn;
-        *reinterpret_cast<floatx4 *>(a.p_out + off) = pn;
+        *reinterpret_cast<floatx4 *>(q_out + off) = qn;
+        *reinterpret_cast<floatx4 *>(p_out + off) = pn;
         if (a.mask_out) *reinterpret_cast<uint32_t *>(a.mask_out + off) = mk;
       }
     }
   }
+}
+
+template <class C, int ORDER, int WALL>
+__global__ __launch_bounds__(C::NT) void step_f32_kernel(StepArgs a) {
+  __shared__ __attribute__((aligned(16))) float smem[C::LDS_FLOATS];
+  step_tile<C, ORDER, WALL>(a, a.J, a.q_in, a.p_in, a.q_out, a.p_out, a.ld, blockIdx.x * C::BM,
+                            blockIdx.y * C::BN, smem);
+}
+
+// Batched form: one launch advances every instance of a batch by one step.
+// Work item w = (instance, row tile, column tile); items are ordered by
+// decreasing contraction length so the longest tiles start first.
+template <class C, int ORDER, int WALL>
+__global__ __launch_bounds__(C::NT) void step_batch_f32_kernel(StepArgs a,
+                                                               const BatchDesc *__restrict__ descs,
+                                                               const int4 *__restrict__ items,
+                                                               int cur) {
+  __shared__ __attribute__((aligned(16))) float smem[C::LDS_FLOATS];
+  const int4 it = items[blockIdx.x];
+  const BatchDesc d = descs[it.x];
+  step_tile<C, ORDER, WALL>(a, d.J, cur ? d.q1 : d.q0, cur ? d.p1 : d.p0, cur ? d.q0 : d.q1,
+                            cur ? d.p0 : d.p1, d.n_pad, it.y * C::BM, it.z * C::BN, smem);
 }
 
 // Tile table: id, BM, BN, waves (WM x WN), MFMA block edge, slab depth BK,
@@ -165,6 +191,23 @@ static hipError_t launch_cfg(const StepArgs &a, hipStream_t s) {
     case 1: step_f32_kernel<C, SI_ORDER_PAPER, SI_WALL_INELASTIC><<<grid, block, 0, s>>>(a); break;
     case 2: step_f32_kernel<C, SI_ORDER_SYMPLECTIC, SI_WALL_CLAMP><<<grid, block, 0, s>>>(a); break;
     case 3: step_f32_kernel<C, SI_ORDER_SYMPLECTIC, SI_WALL_INELASTIC><<<grid, block, 0, s>>>(a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// Batched tiles: 64 x 64, 32x32x2 MFMA, direct-to-LDS ring (4 stages).
+using BatchCfg = F32Cfg<BATCH_BM, BATCH_BN, 2, 2, 32, 32, 4, 1>;
+
+hipError_t launch_step_batch_f32(const StepArgs &a, const BatchDesc *descs, const int4 *items,
+                                 int32_t n_items, int32_t cur, hipStream_t s) {
+  if (n_items <= 0) return hipSuccess;
+  dim3 grid(n_items), block(BatchCfg::NT);
+  switch (a.order * 2 + a.wall) {
+    case 0: step_batch_f32_kernel<BatchCfg, SI_ORDER_PAPER, SI_WALL_CLAMP><<<grid, block, 0, s>>>(a, descs, items, cur); break;
+    case 1: step_batch_f32_kernel<BatchCfg, SI_ORDER_PAPER, SI_WALL_INELASTIC><<<grid, block, 0, s>>>(a, descs, items, cur); break;
+    case 2: step_batch_f32_kernel<BatchCfg, SI_ORDER_SYMPLECTIC, SI_WALL_CLAMP><<<grid, block, 0, s>>>(a, descs, items, cur); break;
+    case 3: step_batch_f32_kernel<BatchCfg, SI_ORDER_SYMPLECTIC, SI_WALL_INELASTIC><<<grid, block, 0, s>>>(a, descs, items, cur); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -115,3 +115,72 @@ def random_state(n: int, r: int, seed: int, scale: float = 1.5) -> np.ndarray:
         x[:, 2] = np.float32(np.sqrt(2.0))
         x[:, 3] = -np.float32(np.sqrt(2.0))
     return x
+
+
+# ---------------------------------------------------------------------------
+# The same streams drawn with torch int64 arithmetic (two's-complement
+# wrap-around equals arithmetic mod 2**64; logical shifts are emulated by
+# masking), so large instances can be generated directly in device memory.
+# Bit-identical to the NumPy functions above.
+# ---------------------------------------------------------------------------
+def _s64(v: int) -> int:
+    v &= 0xFFFFFFFFFFFFFFFF
+    return v - (1 << 64) if v >= (1 << 63) else v
+
+
+def _lsr(z, s: int):
+    import torch
+    return (z >> s) & torch.tensor((1 << (64 - s)) - 1, dtype=torch.int64, device=z.device)
+
+
+def splitmix64_torch(seed: int, count: int, device, start: int = 0):
+    import torch
+    k = torch.arange(start + 1, start + count + 1, dtype=torch.int64, device=device)
+    z = k * _s64(0x9E3779B97F4A7C15) + _s64(seed)
+    z = (z ^ _lsr(z, 30)) * _s64(0xBF58476D1CE4E5B9)
+    z = (z ^ _lsr(z, 27)) * _s64(0x94D049BB133111EB)
+    return z ^ _lsr(z, 31)
+
+
+def _mirror_upper_torch(n, upper, device):
+    import torch
+    J = torch.zeros((n, n), dtype=torch.float32, device=device)
+    iu = torch.triu_indices(n, n, 1, device=device)
+    J[iu[0], iu[1]] = upper
+    J[iu[1], iu[0]] = upper
+    return J
+
+
+def make_pm1_torch(n: int, seed: int = 0, device="cpu"):
+    import torch
+    m = n * (n - 1) // 2
+    z = splitmix64_torch(seed ^ _SALT_J, m, device)
+    upper = torch.where(z < 0, 1.0, -1.0).to(torch.float32)  # bit 63 set <=> negative
+    return _mirror_upper_torch(n, upper, device)
+
+
+def make_gauss_torch(n: int, seed: int = 0, device="cpu"):
+    import math
+
+    import torch
+    m = n * (n - 1) // 2
+    raw = _lsr(splitmix64_torch(seed ^ _SALT_GAUSS, 2 * m, device), 11)
+    u1 = (raw[0::2].to(torch.float64) + 1.0) * 2.0 ** -53
+    u2 = raw[1::2].to(torch.float64) * 2.0 ** -53
+    z = torch.sqrt(-2.0 * torch.log(u1)) * torch.cos(2.0 * math.pi * u2)
+    return _mirror_upper_torch(n, z.to(torch.float32), device)
+
+
+def make_x0_torch(n: int, r: int, seed: int = 0, scale: float = 0.1, device="cpu"):
+    import torch
+    raw = _lsr(splitmix64_torch(seed ^ _SALT_X0, n * r, device), 11)
+    u = raw.to(torch.float64) * 2.0 ** -53
+    return (-scale + 2.0 * scale * u).to(torch.float32).reshape(r, n)
+
+
+def make_J_torch(n: int, kind: str, seed: int, device="cpu"):
+    if kind == "pm1":
+        return make_pm1_torch(n, seed, device)
+    if kind == "gauss":
+        return make_gauss_torch(n, seed, device)
+    raise ValueError(f"unknown instance kind {kind!r}")

@@ -86,6 +86,8 @@ _SIGNATURES = {
     "spring_ising_set_state": [_P, _P, _P, _I],
     "spring_ising_info": [_P, ctypes.POINTER(si_info)],
     "spring_ising_relaxed_energy_grad": [_P, _I, _P, _P, _P],
+    "spring_ising_init_batch": [ctypes.POINTER(_P), _I, _P, _I, _P, _P,
+                                ctypes.POINTER(si_params), _P],
     "spring_ising_destroy": [_P],
 }
 
@@ -163,6 +165,27 @@ def spring_ising_init(n, r, J, x0, p0=None, params=None, stream=None):
     return ctx
 
 
+def spring_ising_init_batch(ns, r, Js, x0s, params, stream=None):
+    """Js, x0s: lists of CUDA float32 tensors (n_i*n_i and r*n_i elements)."""
+    import torch
+    lib = load_library()
+    k = len(ns)
+    if not (len(Js) == len(x0s) == k):
+        raise ValueError("one J and one x0 per instance")
+    n_arr = (ctypes.c_int32 * k)(*[int(v) for v in ns])
+    j_arr = (ctypes.c_void_p * k)(*[_ptr(Js[i], torch.float32, ns[i] * ns[i], "J").value
+                                    for i in range(k)])
+    x_arr = (ctypes.c_void_p * k)(*[_ptr(x0s[i], torch.float32, ns[i] * r, "x0").value
+                                    for i in range(k)])
+    ctx = ctypes.c_void_p()
+    st = lib.spring_ising_init_batch(ctypes.byref(ctx), k, ctypes.cast(n_arr, ctypes.c_void_p),
+                                     int(r), ctypes.cast(j_arr, ctypes.c_void_p),
+                                     ctypes.cast(x_arr, ctypes.c_void_p), ctypes.byref(params),
+                                     stream if stream is not None else _stream())
+    _check(st)
+    return ctx
+
+
 def spring_ising_set_schedule(ctx, dt, zeta):
     import torch
     _check(load_library().spring_ising_set_schedule(ctx, _ptr(dt, torch.float32, name="dt"),
@@ -232,6 +255,83 @@ def spring_ising_destroy(ctx):
 
 
 # ------------------------------------------------------------ convenience
+class SpringIsingBatch:
+    """Owns one batched context: instances of uneven size stepped together.
+
+    Js: list of [N_i, N_i] float32 CUDA tensors; x0s: list of [R, N_i].
+    Outputs are lists per instance.
+    """
+
+    def __init__(self, Js, x0s, total_steps=1000, **overrides):
+        import torch
+        self.ns = [int(J.shape[0]) for J in Js]
+        self.r = int(x0s[0].shape[0])
+        prm = spring_ising_default_params(total_steps)
+        for key, val in overrides.items():
+            setattr(prm, key, val)
+        self.total_steps = int(prm.total_steps)
+        self.device = Js[0].device
+        keep = ([J.contiguous() for J in Js], [x.contiguous() for x in x0s])
+        self.ctx = spring_ising_init_batch(self.ns, self.r, keep[0], keep[1], prm)
+        torch.cuda.current_stream().synchronize()
+        self.offsets = [0]
+        for n in self.ns:
+            self.offsets.append(self.offsets[-1] + self.r * n)
+
+    def close(self):
+        if self.ctx is not None:
+            spring_ising_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def run(self, n_steps):
+        spring_ising_run(self.ctx, n_steps)
+
+    def step(self):
+        spring_ising_step(self.ctx)
+
+    def _split(self, flat):
+        return [flat[self.offsets[i]:self.offsets[i + 1]].view(self.r, n)
+                for i, n in enumerate(self.ns)]
+
+    def state(self):
+        import torch
+        x = torch.empty(self.offsets[-1], dtype=torch.float32, device=self.device)
+        p = torch.empty_like(x)
+        t = spring_ising_get_state(self.ctx, x, p)
+        return self._split(x), self._split(p), t
+
+    def set_state(self, xs, ps=None, t=0):
+        import torch
+        x = torch.cat([v.reshape(-1) for v in xs]).contiguous()
+        p = None if ps is None else torch.cat([v.reshape(-1) for v in ps]).contiguous()
+        spring_ising_set_state(self.ctx, x, p, t)
+        torch.cuda.current_stream().synchronize()
+
+    def spins(self):
+        import torch
+        s = torch.empty(self.offsets[-1], dtype=torch.int8, device=self.device)
+        spring_ising_spins(self.ctx, s)
+        return self._split(s)
+
+    def energy(self, exact=False):
+        import torch
+        k = len(self.ns)
+        e_real = torch.empty(k * self.r, dtype=torch.float64, device=self.device)
+        e_int = torch.empty(k * self.r, dtype=torch.int32, device=self.device) if exact else None
+        spring_ising_energy(self.ctx, e_int, e_real)
+        e = e_int if exact else e_real
+        return [e[i * self.r:(i + 1) * self.r] for i in range(k)]
+
+    def info(self):
+        return spring_ising_info(self.ctx)
+
+
 class SpringIsing:
     """Owns one context; torch tensors carry inputs and outputs.
 
