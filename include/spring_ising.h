@@ -178,6 +178,21 @@ si_status spring_ising_step(si_ctx *ctx);
  * t + n_steps > total_steps.  Asynchronous: no host round trip per step. */
 si_status spring_ising_run(si_ctx *ctx, int32_t n_steps);
 
+/* Execute run() calls of at least min_steps steps as HIP graphs: the launch
+ * sequence of such a call is captured once (keyed by its start step, length
+ * and buffer parity; up to four are kept) and replayed as one graph launch.
+ * Results are bit-identical to direct launches.  0 turns graphs off. */
+si_status spring_ising_set_graph(si_ctx *ctx, int32_t min_steps);
+
+/* Autotuner: time `steps` steps of every step kernel that can serve this
+ * context (its precision and padded shape), starting from the current state,
+ * restore the state after each candidate, and keep the fastest for later
+ * steps.  *best_tile and *best_us (host, nullable) receive the choice and its
+ * time per step.  Kernels with a different MFMA shape add the contraction in
+ * a different order, so later trajectories may differ in the last bits.
+ * Synchronises once per candidate. */
+si_status spring_ising_autotune(si_ctx *ctx, int32_t steps, int32_t *best_tile, float *best_us);
+
 /* Readout: s[r*n + i] = +1 if q_i >= 0 (also -0.0), else -1 (device int8). */
 si_status spring_ising_spins(si_ctx *ctx, int8_t *s);
 

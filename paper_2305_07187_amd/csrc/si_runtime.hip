@@ -108,6 +108,15 @@ struct si_ctx {
   int4 *b_items = nullptr;
   int32_t b_max_npad = 0;
   int64_t b_total_n = 0;
+  // captured HIP graphs of run(n) launch sequences, keyed by (t0, n, cur)
+  struct GraphEntry {
+    int32_t t0, n, cur;
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+  };
+  std::vector<GraphEntry> graphs;
+  int32_t graph_min_steps = 0;  // 0: graphs off
+  hipStream_t cap_stream = nullptr;
   // adjoint workspace
   float *adj_ckpt = nullptr, *adj_seg = nullptr, *adj_lam = nullptr;
   uint8_t *adj_mask = nullptr;
@@ -124,7 +133,16 @@ struct si_ctx {
     *ptr = static_cast<T *>(raw);
     return hipSuccess;
   }
+  void drop_graphs() {
+    for (auto &g : graphs) {
+      (void)hipGraphExecDestroy(g.exec);
+      (void)hipGraphDestroy(g.graph);
+    }
+    graphs.clear();
+  }
   ~si_ctx() {
+    drop_graphs();
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
     for (void *a : allocs) (void)hipFree(a);
   }
 };
@@ -210,7 +228,7 @@ static int32_t choose_tile_bf16(int32_t n, int32_t r, int num_cus, int32_t preci
 static int32_t choose_tile(int32_t n, int32_t r, int num_cus) {
   // Preference from a tile sweep at N=2000, R=1024 on MI355X: 64x64 tiles
   // (two workgroups per CU) with the 32x32x2 MFMA and 64-deep slabs lead.
-  const int32_t order[] = {9, 2, 12, 6, 3};
+  const int32_t order[] = {2, 19, 9, 12, 6, 3};
   int32_t best = 3;
   int64_t best_tiles = -1;
   for (int32_t t : order) {
@@ -716,13 +734,131 @@ si_status spring_ising_step(si_ctx *c) {
   return do_steps(c, 1);
 }
 
+// Replay of a captured launch sequence: the graph holds exactly the launches
+// do_steps would issue for (t0, n, cur), so the result is bit-identical.
+static si_status run_graph(si_ctx *c, int32_t n_steps) {
+  si_ctx::GraphEntry *hit = nullptr;
+  for (auto &g : c->graphs)
+    if (g.t0 == c->t && g.n == n_steps && g.cur == c->cur) hit = &g;
+  if (!hit) {
+    if (!c->cap_stream) SI_HIP(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    if (c->graphs.size() >= 4) {
+      (void)hipGraphExecDestroy(c->graphs.front().exec);
+      (void)hipGraphDestroy(c->graphs.front().graph);
+      c->graphs.erase(c->graphs.begin());
+    }
+    si_ctx::GraphEntry e{c->t, n_steps, c->cur, nullptr, nullptr};
+    const int32_t t_save = c->t, cur_save = c->cur;
+    hipStream_t user = c->stream;
+    c->stream = c->cap_stream;
+    SI_HIP(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed));
+    si_status st = do_steps(c, n_steps);
+    hipError_t ce = hipStreamEndCapture(c->cap_stream, &e.graph);
+    c->stream = user;
+    c->t = t_save;
+    c->cur = cur_save;
+    if (st != SI_OK) return st;
+    SI_HIP(c, ce);
+    SI_HIP(c, hipGraphInstantiate(&e.exec, e.graph, nullptr, nullptr, 0));
+    c->graphs.push_back(e);
+    hit = &c->graphs.back();
+  }
+  SI_HIP(c, hipGraphLaunch(hit->exec, c->stream));
+  c->t += n_steps;
+  c->cur ^= (n_steps & 1);
+  return SI_OK;
+}
+
 si_status spring_ising_run(si_ctx *c, int32_t n_steps) {
   SI_USABLE(c);
   if (n_steps < 0) return fail(SI_ERR_INVALID, "run: n_steps=%d < 0", n_steps);
   if ((int64_t)c->t + n_steps > c->prm.total_steps)
     return fail(SI_ERR_RANGE, "run: t=%d + n_steps=%d exceeds total_steps=%d", c->t, n_steps,
                 c->prm.total_steps);
+  if (c->graph_min_steps > 0 && n_steps >= c->graph_min_steps) return run_graph(c, n_steps);
   return do_steps(c, n_steps);
+}
+
+si_status spring_ising_set_graph(si_ctx *c, int32_t min_steps) {
+  SI_USABLE(c);
+  if (min_steps < 0) return fail(SI_ERR_INVALID, "set_graph: min_steps < 0");
+  c->graph_min_steps = min_steps;
+  if (min_steps == 0) c->drop_graphs();
+  return SI_OK;
+}
+
+// Time every step kernel that can serve this context from its current state
+// and keep the fastest.  The state and step index are restored after each
+// candidate (one host synchronisation per candidate).
+si_status spring_ising_autotune(si_ctx *c, int32_t steps, int32_t *best_tile, float *best_us) {
+  SI_USABLE(c);
+  if (steps < 1) return fail(SI_ERR_INVALID, "autotune: steps < 1");
+  if (c->n_inst) return fail(SI_ERR_UNSUPPORTED, "autotune: not available for a batch");
+  if ((int64_t)c->t + steps > c->prm.total_steps)
+    return fail(SI_ERR_RANGE, "autotune: %d steps from t=%d exceed total_steps", steps, c->t);
+  const int64_t NR = (int64_t)c->n_pad * c->r_pad;
+  float *save = nullptr;
+  uint16_t *save_b = nullptr;
+  if (!c->adj_seg || c->adj_seg_cap < 2 * NR) {
+    SI_HIP(c, c->alloc(&c->adj_seg, 2 * NR));
+    SI_HIP(c, c->alloc(&c->adj_mask, NR));
+    c->adj_seg_cap = 2 * NR;
+  }
+  save = c->adj_seg;
+  if (c->qplanes) SI_HIP(c, c->alloc(&save_b, NR * c->qplanes));
+  const int32_t t0 = c->t, cur0 = c->cur, tile0 = c->tile;
+  SI_HIP(c, hipMemcpyAsync(save, c->q[cur0], NR * 4, hipMemcpyDeviceToDevice, c->stream));
+  SI_HIP(c, hipMemcpyAsync(save + NR, c->p[cur0], NR * 4, hipMemcpyDeviceToDevice, c->stream));
+  if (save_b)
+    SI_HIP(c, hipMemcpyAsync(save_b, c->qb[cur0], NR * 2 * c->qplanes, hipMemcpyDeviceToDevice,
+                             c->stream));
+  hipEvent_t e0, e1;
+  SI_HIP(c, hipEventCreate(&e0));
+  SI_HIP(c, hipEventCreate(&e1));
+  const bool lowp = c->qplanes != 0;
+  const int32_t last = lowp ? TILE_BF16_LAST : TILE_F32_LAST;
+  int32_t best = tile0;
+  float best_t = 1e30f;
+  for (int32_t tile = 1; tile <= last; ++tile) {
+    if (lowp && !tile_valid_bf16(tile, c->prm.precision)) continue;
+    const TileShape ts = shape_of(c->prm.precision, tile);
+    if (c->n_pad % ts.bm || c->r_pad % ts.bn) continue;
+    c->tile = tile;
+    si_status st = do_steps(c, 1);  // warm-up (also loads the code object)
+    if (st == SI_OK) {
+      SI_HIP(c, hipEventRecord(e0, c->stream));
+      st = do_steps(c, steps - 1 > 0 ? steps - 1 : 1);
+      SI_HIP(c, hipEventRecord(e1, c->stream));
+    }
+    // restore the state for the next candidate
+    SI_HIP(c, hipMemcpyAsync(c->q[cur0], save, NR * 4, hipMemcpyDeviceToDevice, c->stream));
+    SI_HIP(c, hipMemcpyAsync(c->p[cur0], save + NR, NR * 4, hipMemcpyDeviceToDevice, c->stream));
+    if (save_b)
+      SI_HIP(c, hipMemcpyAsync(c->qb[cur0], save_b, NR * 2 * c->qplanes, hipMemcpyDeviceToDevice,
+                               c->stream));
+    c->t = t0;
+    c->cur = cur0;
+    if (st != SI_OK) {
+      c->poisoned = false;  // a candidate the device cannot launch is skipped
+      (void)hipGetLastError();
+      continue;
+    }
+    SI_HIP(c, hipEventSynchronize(e1));
+    float ms = 0.f;
+    SI_HIP(c, hipEventElapsedTime(&ms, e0, e1));
+    const float us = 1000.f * ms / (float)(steps - 1 > 0 ? steps - 1 : 1);
+    if (us < best_t) {
+      best_t = us;
+      best = tile;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  c->tile = best;
+  c->drop_graphs();
+  if (best_tile) *best_tile = best;
+  if (best_us) *best_us = best_t;
+  return SI_OK;
 }
 
 
@@ -877,7 +1013,7 @@ si_status spring_ising_info(si_ctx *c, si_info *info) {
   info->j_bf16_exact = c->hflags[5] == 0;
   info->tile = c->tile;
   info->precision = c->prm.precision;
-  info->graph_steps = 0;
+  info->graph_steps = c->graph_min_steps;
   info->device_bytes = c->bytes;
   if (c->n_inst)
     snprintf(info->kernel_name, sizeof info->kernel_name, "step_batch_f32_%dx%d_x%d", BATCH_BM,

@@ -86,6 +86,8 @@ _SIGNATURES = {
     "spring_ising_set_state": [_P, _P, _P, _I],
     "spring_ising_info": [_P, ctypes.POINTER(si_info)],
     "spring_ising_relaxed_energy_grad": [_P, _I, _P, _P, _P],
+    "spring_ising_set_graph": [_P, _I],
+    "spring_ising_autotune": [_P, _I, ctypes.POINTER(_I), ctypes.POINTER(ctypes.c_float)],
     "spring_ising_init_batch": [ctypes.POINTER(_P), _I, _P, _I, _P, _P,
                                 ctypes.POINTER(si_params), _P],
     "spring_ising_destroy": [_P],
@@ -242,6 +244,18 @@ def spring_ising_relaxed_energy_grad(ctx, ckpt_every, loss, dl_ddt, dl_dzeta):
     _check(load_library().spring_ising_relaxed_energy_grad(
         ctx, int(ckpt_every), _ptr(loss, torch.float64, 1, "loss"),
         _ptr(dl_ddt, torch.float64, name="dL_ddt"), _ptr(dl_dzeta, torch.float64, name="dL_dzeta")))
+
+
+def spring_ising_set_graph(ctx, min_steps):
+    _check(load_library().spring_ising_set_graph(ctx, int(min_steps)))
+
+
+def spring_ising_autotune(ctx, steps):
+    tile = ctypes.c_int32()
+    us = ctypes.c_float()
+    _check(load_library().spring_ising_autotune(ctx, int(steps), ctypes.byref(tile),
+                                                ctypes.byref(us)))
+    return tile.value, us.value
 
 
 def spring_ising_info(ctx) -> dict:
@@ -419,6 +433,12 @@ class SpringIsing:
 
     def info(self):
         return spring_ising_info(self.ctx)
+
+    def set_graph(self, min_steps):
+        spring_ising_set_graph(self.ctx, min_steps)
+
+    def autotune(self, steps=20):
+        return spring_ising_autotune(self.ctx, steps)
 
     def relaxed_energy_grad(self, ckpt_every=100):
         """Run the remaining steps; return (loss, dL/ddt, dL/dzeta) as float64

@@ -1,0 +1,94 @@
+"""Runtime features: HIP-graph replay of run() and the autotuner."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2305_07187_amd import instances
+
+from gpu_common import QMAX, announce, ensure_built, oracle_schedules, rel_err, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x_fp8j", "bf16x3_exactj"])
+def test_graph_replays_match_direct_launches(precision):
+    import torch
+    si = ensure_built()
+    announce(f"graph replay vs direct launches ({precision})")
+    n, r, S = 500, 128, 400
+    J = to_dev(instances.make_pm1(n, 2))
+    x0 = to_dev(instances.make_x0(n, r, 2))
+    direct = si.SpringIsing(J, x0, total_steps=S, precision=precision)
+    direct.run(S)
+    xd, pd, _ = direct.state()
+    ed = direct.energy()
+    torch.cuda.synchronize()
+    g = si.SpringIsing(J, x0, total_steps=S, precision=precision)
+    g.set_graph(50)
+    assert g.info()["graph_steps"] == 50
+    for rep in range(3):
+        g.set_state(x0, None, 0)
+        g.run(S)
+        xg, pg, t = g.state()
+        eg = g.energy()           # eager work between replays
+        torch.cuda.synchronize()
+        assert t == S
+        assert torch.equal(xg, xd) and torch.equal(pg, pd) and torch.equal(eg, ed), rep
+    # a different start and length is captured separately
+    g.set_state(x0, None, 0)
+    g.run(150)
+    g.run(S - 150)
+    xg, _, _ = g.state()
+    torch.cuda.synchronize()
+    assert torch.equal(xg, xd)
+    direct.close()
+    g.close()
+
+
+def test_graph_on_batch():
+    import torch
+    si = ensure_built()
+    announce("graph replay on a batch")
+    specs = [(64, "pm1"), (300, "gauss"), (129, "pm1")]
+    Js = [to_dev(instances.make_J(n, k, i)) for i, (n, k) in enumerate(specs)]
+    xs = [to_dev(instances.make_x0(n, 64, i)) for i, (n, k) in enumerate(specs)]
+    a = si.SpringIsingBatch(Js, xs, total_steps=100)
+    a.run(100)
+    xa, _, _ = a.state()
+    b = si.SpringIsingBatch(Js, xs, total_steps=100)
+    si.spring_ising_set_graph(b.ctx, 10)
+    b.run(100)
+    xb, _, _ = b.state()
+    torch.cuda.synchronize()
+    for u, v in zip(xa, xb):
+        assert torch.equal(u, v)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x_bf16j"])
+def test_autotune_keeps_state_and_parity(precision):
+    import torch
+    si = ensure_built()
+    announce(f"autotune ({precision})")
+    n, r, S = 100, 8, 1000
+    Jn = instances.make_pm1(n, 0)
+    x0n = instances.make_x0(n, r, 0)
+    m = si.SpringIsing(to_dev(Jn), to_dev(x0n), total_steps=S, precision=precision)
+    m.run(3)
+    x_before, p_before, t_before = m.state()
+    tile, us = m.autotune(5)
+    x_after, p_after, t_after = m.state()
+    torch.cuda.synchronize()
+    info = m.info()
+    announce(f"  chose tile {tile} ({info['kernel_name']}) at {us:.2f} us/step")
+    assert info["tile"] == tile and us > 0
+    assert t_after == t_before == 3
+    assert torch.equal(x_before, x_after) and torch.equal(p_before, p_after)
+    if precision == "fp32":
+        m.run(47)
+        x, _, _ = m.state()
+        torch.cuda.synchronize()
+        dt, zeta = oracle_schedules(S)
+        ref = oracle.run(Jn.astype(np.float64), x0n.T.astype(np.float64), None, dt, zeta,
+                         qmax=QMAX, n_steps=50)
+        assert rel_err(x.cpu().numpy(), ref["Q"]) <= 1e-5
+    m.close()
