@@ -39,6 +39,13 @@ PEAK_FP32_MFMA_TFLOPS = 157.3
 PEAK_BF16_MFMA_TFLOPS = 2500.0
 PEAK_HBM_GBS = 8000.0
 FORMS = ["bf16x_fp8j", "bf16x_bf16j", "bf16x3_exactj"]
+# HBM/MALL bytes per launch of a step kernel at this workload, from two
+# rocprofv3 counter passes (FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000; the
+# factors come from an elementwise kernel of known size in the same runs).
+# Keyed by kernel name; an entry is removed whenever that kernel changes.
+MEASURED_TRAFFIC_BYTES = {
+    "step_f32_64x64_w2x2_mfma32_k32_s0_a1": 114.67e6,
+}
 
 
 def cpu_baseline(budget_s: float = 15.0):
@@ -131,7 +138,8 @@ def main():
     ap.add_argument("--precision", default="fp32", help="fp32 | bf16x_fp8j | bf16x_bf16j | "
                     "bf16x_hiloj | bf16x3_exactj (the headline line is fp32)")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
-                    help="first run one device copy of this many MiB (counter calibration)")
+                    help="first run one elementwise kernel reading and writing this many MiB "
+                         "(calibration of the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the replica-"
@@ -151,9 +159,10 @@ def main():
     dev = torch.device("cuda:0")
     iters = args.iters
     if args.calib_copy_mb:
+        # one elementwise kernel that reads and writes calib_copy_mb MiB each
         src = torch.ones(args.calib_copy_mb * 262144, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
-        dst.copy_(src)
+        torch.mul(src, 2.0, out=dst)
         torch.cuda.synchronize()
         del src, dst
     Jn = instances.make_pm1(N, 0)
@@ -191,7 +200,9 @@ def main():
                    "n": N, "replicas": R, "iterations": iters, "precision": args.precision,
                    "kernel": info["kernel_name"]},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": None,
+                     "frac": achieved / peak,
+                     "traffic": MEASURED_TRAFFIC_BYTES.get(info["kernel_name"]),
+                     "traffic_unit": "bytes per launch",
                      "kernel": info["kernel_name"], "avg_launch_us": kernel_us,
                      "algorithmic_flop_per_launch": flops},
         "result": {"best_cut": float(cuts.max()), "mean_cut": float(cuts.mean()),
