@@ -203,6 +203,23 @@ si_status spring_ising_spins(si_ctx *ctx, int8_t *s);
  *           real J it is an FP32 product with a compensated FP32 sum. */
 si_status spring_ising_energy(si_ctx *ctx, int32_t *e_int, double *e_real);
 
+/* In-run best state: evaluate the energy of the current spins (exactly for
+ * integer J, else as the real energy) and keep, per replica, the lowest value
+ * seen since init or the last set_state together with its spins. */
+si_status spring_ising_update_best(si_ctx *ctx);
+
+/* Copy the recorded best energies (device, r doubles) and spins (device,
+ * r*n int8, replica-major); either may be NULL.  SI_ERR_STATE before the
+ * first update_best. */
+si_status spring_ising_get_best(si_ctx *ctx, double *best_e, int8_t *best_s);
+
+/* Hamiltonian of the spring system, Eq. (7), per replica (device, r
+ * doubles): sum_i p_i^2/(2m) + k q_i^2/2 + zeta_t H_Ising(q) with the
+ * continuous Ising energy H_Ising(q) = -1/2 q^T J q - h.q and zeta_t the
+ * schedule value of the current step (the last one once the run is over).
+ * FP32 products, compensated FP32 sums. */
+si_status spring_ising_hamiltonian(si_ctx *ctx, double *H);
+
 /* Copy the state out: x, p device r*n floats (either may be NULL); *t (host,
  * may be NULL) receives the step index. */
 si_status spring_ising_get_state(si_ctx *ctx, float *x, float *p, int32_t *t);

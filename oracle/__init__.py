@@ -19,6 +19,7 @@ exact rational replays and finite differences, never against itself.
 from .spring_ising import (  # noqa: F401
     PAPER,
     cut_value,
+    hamiltonian,
     ising_energy,
     ising_energy_pairs,
     relaxed_energy,

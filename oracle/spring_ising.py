@@ -132,6 +132,19 @@ def relaxed_energy(J, Q):
     return float(per.mean())
 
 
+def hamiltonian(J, Q, P, zeta, k=PAPER["k"], m=PAPER["m"], h=None):
+    """Eq. (7) per replica with q0 = 0 and qdot = p/m:
+    H = sum_i p_i^2/(2m) + sum_i k q_i^2/2 + zeta * H_Ising(q), where
+    H_Ising(q) = -1/2 q^T J q - h.q is Eq. (1) with the spins relaxed to q."""
+    J = np.asarray(J, dtype=np.float64)
+    Q = np.asarray(Q, dtype=np.float64)
+    P = np.asarray(P, dtype=np.float64)
+    ising = -0.5 * np.einsum("ir,ij,jr->r", Q, J, Q)
+    if h is not None:
+        ising = ising - np.asarray(h, dtype=np.float64) @ Q
+    return (P * P).sum(axis=0) / (2.0 * m) + 0.5 * k * (Q * Q).sum(axis=0) + zeta * ising
+
+
 # --------------------------------------------------------------------------
 # zeta(t) and Delta schedules
 # --------------------------------------------------------------------------

@@ -12,7 +12,7 @@ namespace si {
 // Tile ids of the FP32 step kernel (see the tile table in si_step_f32.hip);
 // 0 selects automatically.
 constexpr int32_t TILE_AUTO = 0;
-constexpr int32_t TILE_F32_LAST = 24;
+constexpr int32_t TILE_F32_LAST = 34;
 
 struct TileShape {
   int32_t bm, bn;
@@ -80,7 +80,16 @@ hipError_t launch_energy_f32_partial(const float *J, const float *q, const float
                                      float *part, int32_t n_pad, int32_t r_pad,
                                      hipStream_t s);
 hipError_t launch_energy_f32_finalize(const float *part, int32_t n_tiles, int32_t r,
-                                      int32_t r_pad, double *e_real, hipStream_t s);
+                                      int32_t r_pad, double *e_real, hipStream_t s,
+                                      float scale = -0.5f);
+// Eq. (7) Hamiltonian per replica (partials per row tile, add with scale 1).
+hipError_t launch_hamiltonian_partial(const float *J, const float *q, const float *p,
+                                      const float *h, const float *zetas, int32_t t, float k,
+                                      float inv_m, float *part, int32_t n_pad, int32_t r_pad,
+                                      hipStream_t s);
+hipError_t launch_best_update(const double *e, double *best_e, const int8_t *S8, int8_t *best_s,
+                              int32_t r, int32_t n_pad, hipStream_t s);
+hipError_t launch_fill_f64(double *p, int64_t count, double v, hipStream_t s);
 
 // Exact energy: s = sign(q) as int8 into S8, then G = J8.S8 on int8 MFMA,
 // acc[r] += sum_i s_i (G_i + 2 h_i), then e[r] = -acc[r]/2.
@@ -106,7 +115,6 @@ hipError_t launch_adj_step(const float *J, const float *lamq_in, const float *la
 hipError_t launch_adj_reduce(const double *part, int32_t nwg, int32_t mode, double *loss,
                              double *g_dt, double *g_zeta, const float *dt, const float *zeta,
                              int32_t n, float k, float inv_m, int32_t r_count, hipStream_t s);
-hipError_t launch_fill_f64(double *p, int64_t count, double v, hipStream_t s);
 
 // Layout conversion and validation.
 hipError_t launch_pack_matrix(const float *src, int32_t n, float *dst, int8_t *dst8,

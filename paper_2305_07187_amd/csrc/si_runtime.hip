@@ -117,6 +117,10 @@ struct si_ctx {
   std::vector<GraphEntry> graphs;
   int32_t graph_min_steps = 0;  // 0: graphs off
   hipStream_t cap_stream = nullptr;
+  // in-run best state per replica
+  double *best_e = nullptr, *e_scratch = nullptr;
+  int8_t *best_s = nullptr;
+  bool best_fresh = true;  // next update starts the record
   // adjoint workspace
   float *adj_ckpt = nullptr, *adj_seg = nullptr, *adj_lam = nullptr;
   uint8_t *adj_mask = nullptr;
@@ -228,7 +232,7 @@ static int32_t choose_tile_bf16(int32_t n, int32_t r, int num_cus, int32_t preci
 static int32_t choose_tile(int32_t n, int32_t r, int num_cus) {
   // Preference from a tile sweep at N=2000, R=1024 on MI355X: 64x64 tiles
   // (two workgroups per CU) with the 32x32x2 MFMA and 64-deep slabs lead.
-  const int32_t order[] = {2, 19, 9, 12, 6, 3};
+  const int32_t order[] = {27, 26, 2, 9, 12, 6, 3};
   int32_t best = 3;
   int64_t best_tiles = -1;
   for (int32_t t : order) {
@@ -959,6 +963,60 @@ si_status spring_ising_energy(si_ctx *c, int32_t *e_int, double *e_real) {
   return SI_OK;
 }
 
+static si_status ensure_best(si_ctx *c) {
+  if (!c->best_e) {
+    SI_HIP(c, c->alloc(&c->best_e, c->r_pad));
+    SI_HIP(c, c->alloc(&c->e_scratch, c->r_pad));
+    SI_HIP(c, c->alloc(&c->best_s, (int64_t)c->r_pad * c->n_pad));
+  }
+  return SI_OK;
+}
+
+si_status spring_ising_update_best(si_ctx *c) {
+  SI_USABLE(c);
+  if (c->n_inst) return fail(SI_ERR_UNSUPPORTED, "update_best: not available for a batch");
+  si_status st = ensure_best(c);
+  if (st != SI_OK) return st;
+  if (c->best_fresh) {
+    SI_HIP(c, launch_fill_f64(c->best_e, c->r_pad, __builtin_inf(), c->stream));
+    c->best_fresh = false;
+  }
+  st = spring_ising_energy(c, nullptr, c->e_scratch);
+  if (st != SI_OK) return st;
+  SI_HIP(c, launch_sign(c->q[c->cur], c->S8, c->n_pad, c->r_pad, c->stream));
+  SI_HIP(c, launch_best_update(c->e_scratch, c->best_e, c->S8, c->best_s, c->r, c->n_pad,
+                               c->stream));
+  return SI_OK;
+}
+
+si_status spring_ising_get_best(si_ctx *c, double *best_e, int8_t *best_s) {
+  SI_USABLE(c);
+  if (c->n_inst) return fail(SI_ERR_UNSUPPORTED, "get_best: not available for a batch");
+  if (!c->best_e || c->best_fresh)
+    return fail(SI_ERR_STATE, "get_best: no update_best since init or set_state");
+  if ((best_e && !is_device_ptr(best_e)) || (best_s && !is_device_ptr(best_s)))
+    return fail(SI_ERR_INVALID, "get_best: outputs must be device pointers");
+  if (best_e)
+    SI_HIP(c, hipMemcpyAsync(best_e, c->best_e, sizeof(double) * c->r, hipMemcpyDeviceToDevice,
+                             c->stream));
+  if (best_s)
+    SI_HIP(c, launch_unpack_spins(c->best_s, c->n, c->r, best_s, c->n_pad, c->stream));
+  return SI_OK;
+}
+
+si_status spring_ising_hamiltonian(si_ctx *c, double *H) {
+  SI_USABLE(c);
+  if (c->n_inst) return fail(SI_ERR_UNSUPPORTED, "hamiltonian: not available for a batch");
+  if (!is_device_ptr(H)) return fail(SI_ERR_INVALID, "hamiltonian: H must be a device pointer");
+  const int32_t t = c->t < c->prm.total_steps ? c->t : c->prm.total_steps - 1;
+  SI_HIP(c, launch_hamiltonian_partial(c->J, c->q[c->cur], c->p[c->cur],
+                                       c->has_field ? c->hf : nullptr, c->zeta, t, c->prm.k,
+                                       1.0f / c->prm.m, c->epart, c->n_pad, c->r_pad, c->stream));
+  SI_HIP(c, launch_energy_f32_finalize(c->epart, c->n_pad / 64, c->r, c->r_pad, H, c->stream,
+                                       1.0f));
+  return SI_OK;
+}
+
 si_status spring_ising_get_state(si_ctx *c, float *x, float *p, int32_t *t) {
   SI_USABLE(c);
   if ((x && !is_device_ptr(x)) || (p && !is_device_ptr(p)))
@@ -987,6 +1045,7 @@ si_status spring_ising_set_state(si_ctx *c, const float *x, const float *p, int3
   }
   SI_HIP(c, launch_pack_state(x, c->n, c->r, c->q[c->cur], c->n_pad, c->r_pad, c->stream));
   SI_HIP(c, launch_pack_state(p, c->n, c->r, c->p[c->cur], c->n_pad, c->r_pad, c->stream));
+  c->best_fresh = true;
   if (c->qplanes)
     SI_HIP(c, launch_split_planes(c->q[c->cur], c->qb[c->cur], (int64_t)c->n_pad * c->r_pad,
                                   c->qplanes, c->stream));

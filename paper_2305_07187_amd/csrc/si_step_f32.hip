@@ -167,7 +167,17 @@ __global__ __launch_bounds__(C::NT) void step_batch_f32_kernel(StepArgs a,
   X(21, 64, 64, 2, 1, 32, 32, 4, 1)    \
   X(22, 64, 64, 2, 1, 32, 32, 4, 2)    \
   X(23, 64, 64, 2, 2, 32, 64, 3, 2)    \
-  X(24, 64, 128, 2, 2, 32, 32, 4, 2)
+  X(24, 64, 128, 2, 2, 32, 32, 4, 2)   \
+  X(25, 128, 64, 4, 2, 32, 32, 0, 1)   \
+  X(26, 128, 64, 4, 2, 32, 32, 4, 1)   \
+  X(27, 64, 128, 2, 4, 32, 32, 4, 1)   \
+  X(28, 128, 64, 4, 2, 32, 64, 3, 1)   \
+  X(29, 128, 128, 4, 4, 32, 32, 0, 1)  \
+  X(30, 128, 64, 4, 2, 32, 32, 6, 1)   \
+  X(31, 128, 64, 4, 2, 32, 32, 4, 2)   \
+  X(32, 64, 128, 2, 4, 32, 32, 6, 1)   \
+  X(33, 128, 64, 4, 2, 32, 32, 5, 1)   \
+  X(34, 128, 64, 4, 2, 32, 32, 3, 1)
 
 TileShape tile_shape(int32_t tile) {
   switch (tile) {
@@ -270,7 +280,7 @@ __global__ __launch_bounds__(256) void energy_f32_partial_kernel(const float *J,
   }
 }
 __global__ void energy_f32_finalize_kernel(const float *part, int n_tiles, int r, int r_pad,
-                                           double *e) {
+                                           double *e, float scale) {
   const int col = blockIdx.x * blockDim.x + threadIdx.x;
   if (col >= r) return;
   // Neumaier-compensated FP32 sum over the row tiles, in fixed order.
@@ -284,7 +294,89 @@ __global__ void energy_f32_finalize_kernel(const float *part, int n_tiles, int r
       comp += (x - y) + s;
     s = y;
   }
-  e[col] = -0.5 * ((double)s + (double)comp);
+  e[col] = (double)scale * ((double)s + (double)comp);
+}
+
+// ---------------------------------------------------------------------------
+// Hamiltonian of the spring system, Eq. (7), per replica (q0 = 0, qdot = p/m):
+//   H = sum_i [ p_i^2 / (2m) + k q_i^2 / 2 ] + zeta_t H_Ising(q),
+//   H_Ising(q) = -1/2 q^T J q - h.q  (the continuous Ising energy)
+// = sum_i [ p_i^2/(2m) + k q_i^2/2 - zeta_t q_i (G_i + 2 h_i) / 2 ],  G = J q.
+// Per row tile partial sums; the energy finaliser adds them (scale 1).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void hamiltonian_partial_kernel(
+    const float *J, const float *q, const float *p, const float *h, const float *zetas, int t,
+    float k, float inv_m, float *part, int ld, int r_pad) {
+  __shared__ __attribute__((aligned(16))) float smem[ECfg::LDS_FLOATS];
+  __shared__ float red[ECfg::WM][ECfg::BN];
+  const int m0 = blockIdx.x * ECfg::BM;
+  const int n0 = blockIdx.y * ECfg::BN;
+  ECfg::acc_t acc[ECfg::TM][ECfg::TN];
+  f32_mainloop<ECfg, B_PLAIN>(J, q, ld, ld, m0, n0, acc, smem);
+  const float zeta = zetas[t];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int wy = wave / ECfg::WN, wx = wave % ECfg::WN;
+#pragma unroll
+  for (int j = 0; j < ECfg::TN; ++j) {
+    const int lcol = wx * ECfg::WTN + j * ECfg::MB + (lane % ECfg::MB);
+    float c = 0.f;
+#pragma unroll
+    for (int i = 0; i < ECfg::TM; ++i)
+#pragma unroll
+      for (int g = 0; g < ECfg::M::NACC / 4; ++g) {
+        const int row = m0 + wy * ECfg::WTM + i * ECfg::MB + g * 8 + (lane / ECfg::MB) * 4;
+        const size_t off = (size_t)(n0 + lcol) * ld + row;
+        const floatx4 q4 = *reinterpret_cast<const floatx4 *>(q + off);
+        const floatx4 p4 = *reinterpret_cast<const floatx4 *>(p + off);
+        floatx4 h4 = {0.f, 0.f, 0.f, 0.f};
+        if (h) h4 = *reinterpret_cast<const floatx4 *>(h + row);
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          c += 0.5f * p4[v] * p4[v] * inv_m + 0.5f * k * q4[v] * q4[v] -
+               0.5f * zeta * q4[v] * (acc[i][j][4 * g + v] + 2.f * h4[v]);
+      }
+    for (int off = ECfg::MB; off < 64; off <<= 1) c += __shfl_xor(c, off);
+    if (lane < ECfg::MB) red[wy][lcol] = c;
+  }
+  __syncthreads();
+  if (threadIdx.x < ECfg::BN) {
+    float sum = 0.f;
+#pragma unroll
+    for (int w = 0; w < ECfg::WM; ++w) sum += red[w][threadIdx.x];
+    part[(size_t)blockIdx.x * r_pad + n0 + threadIdx.x] = sum;
+  }
+}
+
+hipError_t launch_hamiltonian_partial(const float *J, const float *q, const float *p,
+                                      const float *h, const float *zetas, int32_t t, float k,
+                                      float inv_m, float *part, int32_t n_pad, int32_t r_pad,
+                                      hipStream_t s) {
+  if (n_pad % ECfg::BM || r_pad % ECfg::BN) return hipErrorInvalidValue;
+  dim3 grid(n_pad / ECfg::BM, r_pad / ECfg::BN);
+  hamiltonian_partial_kernel<<<grid, 256, 0, s>>>(J, q, p, h, zetas, t, k, inv_m, part, n_pad,
+                                                  r_pad);
+  return hipGetLastError();
+}
+
+// Keep, per replica, the lowest energy seen and the spins that had it.
+__global__ void best_update_kernel(const double *e, double *best_e, const int8_t *S8,
+                                   int8_t *best_s, int n_pad) {
+  const int r = blockIdx.x;
+  const double en = e[r];
+  if (!(en < best_e[r])) return;  // block-uniform decision
+  const int8_t *src = S8 + (size_t)r * n_pad;
+  int8_t *dst = best_s + (size_t)r * n_pad;
+  for (int i = threadIdx.x * 4; i < n_pad; i += blockDim.x * 4)
+    *reinterpret_cast<char4 *>(dst + i) = *reinterpret_cast<const char4 *>(src + i);
+  __syncthreads();
+  if (threadIdx.x == 0) best_e[r] = en;
+}
+
+hipError_t launch_best_update(const double *e, double *best_e, const int8_t *S8, int8_t *best_s,
+                              int32_t r, int32_t n_pad, hipStream_t s) {
+  best_update_kernel<<<r, 256, 0, s>>>(e, best_e, S8, best_s, n_pad);
+  return hipGetLastError();
 }
 
 hipError_t launch_energy_f32_partial(const float *J, const float *q, const float *h, float *part,
@@ -296,8 +388,9 @@ hipError_t launch_energy_f32_partial(const float *J, const float *q, const float
 }
 
 hipError_t launch_energy_f32_finalize(const float *part, int32_t n_tiles, int32_t r,
-                                      int32_t r_pad, double *e_real, hipStream_t s) {
-  energy_f32_finalize_kernel<<<(r + 255) / 256, 256, 0, s>>>(part, n_tiles, r, r_pad, e_real);
+                                      int32_t r_pad, double *e_real, hipStream_t s, float scale) {
+  energy_f32_finalize_kernel<<<(r + 255) / 256, 256, 0, s>>>(part, n_tiles, r, r_pad, e_real,
+                                                             scale);
   return hipGetLastError();
 }
 

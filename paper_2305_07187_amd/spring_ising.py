@@ -87,6 +87,9 @@ _SIGNATURES = {
     "spring_ising_info": [_P, ctypes.POINTER(si_info)],
     "spring_ising_relaxed_energy_grad": [_P, _I, _P, _P, _P],
     "spring_ising_set_graph": [_P, _I],
+    "spring_ising_update_best": [_P],
+    "spring_ising_get_best": [_P, _P, _P],
+    "spring_ising_hamiltonian": [_P, _P],
     "spring_ising_autotune": [_P, _I, ctypes.POINTER(_I), ctypes.POINTER(ctypes.c_float)],
     "spring_ising_init_batch": [ctypes.POINTER(_P), _I, _P, _I, _P, _P,
                                 ctypes.POINTER(si_params), _P],
@@ -244,6 +247,21 @@ def spring_ising_relaxed_energy_grad(ctx, ckpt_every, loss, dl_ddt, dl_dzeta):
     _check(load_library().spring_ising_relaxed_energy_grad(
         ctx, int(ckpt_every), _ptr(loss, torch.float64, 1, "loss"),
         _ptr(dl_ddt, torch.float64, name="dL_ddt"), _ptr(dl_dzeta, torch.float64, name="dL_dzeta")))
+
+
+def spring_ising_update_best(ctx):
+    _check(load_library().spring_ising_update_best(ctx))
+
+
+def spring_ising_get_best(ctx, best_e=None, best_s=None):
+    import torch
+    _check(load_library().spring_ising_get_best(ctx, _ptr(best_e, torch.float64, name="best_e"),
+                                                _ptr(best_s, torch.int8, name="best_s")))
+
+
+def spring_ising_hamiltonian(ctx, H):
+    import torch
+    _check(load_library().spring_ising_hamiltonian(ctx, _ptr(H, torch.float64, name="H")))
 
 
 def spring_ising_set_graph(ctx, min_steps):
@@ -433,6 +451,22 @@ class SpringIsing:
 
     def info(self):
         return spring_ising_info(self.ctx)
+
+    def update_best(self):
+        spring_ising_update_best(self.ctx)
+
+    def best(self):
+        import torch
+        e = torch.empty(self.r, dtype=torch.float64, device=self.device)
+        s = torch.empty(self.r, self.n, dtype=torch.int8, device=self.device)
+        spring_ising_get_best(self.ctx, e, s)
+        return e, s
+
+    def hamiltonian(self):
+        import torch
+        H = torch.empty(self.r, dtype=torch.float64, device=self.device)
+        spring_ising_hamiltonian(self.ctx, H)
+        return H
 
     def set_graph(self, min_steps):
         spring_ising_set_graph(self.ctx, min_steps)

@@ -212,3 +212,29 @@ def test_qualitative_descent():
     e1 = oracle.ising_energy(J, oracle.spins(out["Q"]))
     assert np.all(e1 < e0)
     assert np.mean(np.isclose(np.abs(out["Q"]), PAPER["qmax"])) > 0.5
+
+
+# ------------------------------------------------------- Eq. (7) Hamiltonian
+def test_hamiltonian_free_spring_growth():
+    # J = 0: H = (k q^2 + p^2/m)/2, which the paper-order step multiplies by
+    # exactly (1 + Delta^2 k/m) (same identity as the free-spring pin).
+    n, r, S, k, m, dt = 6, 3, 15, 0.5, 2.0, 0.1
+    rng = np.random.default_rng(3)
+    Q0 = rng.uniform(-0.05, 0.05, (n, r))
+    P0 = rng.uniform(-0.05, 0.05, (n, r))
+    out = oracle.run(np.zeros((n, n)), Q0, P0, np.full(S, dt), np.zeros(S), k=k, m=m,
+                     record=range(S + 1))
+    H = [oracle.hamiltonian(np.zeros((n, n)), *out["traj"][s], 0.3, k=k, m=m) for s in range(S + 1)]
+    for s in range(S):
+        np.testing.assert_allclose(H[s + 1], (1 + dt * dt * k / m) * H[s], rtol=1e-13)
+
+
+def test_hamiltonian_at_spin_vertices():
+    # q = s (+-1), p = 0: H = k N/2 + zeta E(s), with E the Eq. (1) energy.
+    n = 40
+    J = instances.make_pm1(n, 6).astype(np.float64)
+    h = np.random.default_rng(2).integers(-2, 3, n).astype(np.float64)
+    S = np.random.default_rng(1).choice([-1.0, 1.0], size=(n, 5))
+    H = oracle.hamiltonian(J, S, np.zeros_like(S), 0.37, k=0.5, h=h)
+    E = oracle.ising_energy(J, S.astype(np.int64), h)
+    np.testing.assert_allclose(H, 0.25 * n + 0.37 * E, rtol=1e-13)
