@@ -14,6 +14,19 @@ namespace si {
 constexpr int32_t TILE_AUTO = 0;
 constexpr int32_t TILE_F32_LAST = 34;
 
+// Work-groups of a launch are dispatched to the eight XCDs in turn (group b
+// runs on XCD b % 8), and each XCD has its own L2.  xcd_tile() renumbers the
+// groups so that every XCD takes one contiguous range of the row-major tile
+// order: the groups resident on an XCD at one time then share rows of J and
+// sweep the same replica columns, so each slab of J reaches that L2 once for
+// all column tiles instead of once per group.
+constexpr int NUM_XCD = 8;
+__device__ __forceinline__ int xcd_tile(int b, int groups) {
+  const int per = groups / NUM_XCD;
+  if (b >= per * NUM_XCD) return b;
+  return (b % NUM_XCD) * per + b / NUM_XCD;
+}
+
 struct TileShape {
   int32_t bm, bn;
   const char *name;
@@ -52,7 +65,7 @@ hipError_t launch_step_batch_f32(const StepArgs &a, const BatchDesc *descs, cons
                                  int32_t n_items, int32_t cur, hipStream_t s);
 
 // Step on the BF16 matrix cores (precision forms).
-constexpr int32_t TILE_BF16_LAST = 13;
+constexpr int32_t TILE_BF16_LAST = 19;
 TileShape tile_shape_bf16(int32_t tile);
 struct BStepArgs {
   const void *Ja;         // J plane: bf16 or fp8 [n_pad][n_pad]

@@ -200,16 +200,18 @@ static TileShape shape_of(int32_t precision, int32_t tile) {
 }
 
 static int32_t choose_tile_bf16(int32_t n, int32_t r, int num_cus, int32_t precision) {
-  // Preference from a tile sweep at N=2000, R=1024 on MI355X (direct-to-LDS
-  // rings first; register-staged tiles as the fallback for small problems).
-  static const int32_t pref_bf16j[] = {8, 7, 11, 10, 1, 2, 3};
-  static const int32_t pref_fp8j[] = {9, 13, 1, 6, 2, 3};
-  static const int32_t pref_hilo[] = {7, 10, 11, 1, 2, 3};
+  // Preference from tile sweeps on MI355X at N=2000 (R=1024 and 2048) and
+  // N=8000 (R=2048): 64x64-wave tiles (128x256, 128x128) once the problem
+  // gives every CU a workgroup of that size, then 64x64 direct-to-LDS rings,
+  // then register-staged tiles as the fallback for small problems.
+  static const int32_t pref_bf16j[] = {16, 18, 8, 7, 11, 10, 1, 2, 3};
+  static const int32_t pref_fp8j[] = {14, 9, 13, 1, 6, 2, 3};
+  static const int32_t pref_hilo[] = {18, 7, 10, 11, 1, 2, 3};
   static const int32_t pref_exact[] = {11, 8, 7, 1, 2, 3};
   const int32_t *order = pref_bf16j;
-  int count = 7;
-  if (precision == SI_PREC_BF16X_FP8J) { order = pref_fp8j; count = 6; }
-  if (precision == SI_PREC_BF16X_HILOJ) { order = pref_hilo; count = 6; }
+  int count = 9;
+  if (precision == SI_PREC_BF16X_FP8J) { order = pref_fp8j; count = 7; }
+  if (precision == SI_PREC_BF16X_HILOJ) { order = pref_hilo; count = 7; }
   if (precision == SI_PREC_BF16X3_EXACTJ) { order = pref_exact; count = 6; }
   int32_t best = 1;
   int64_t best_tiles = -1;
@@ -230,8 +232,15 @@ static int32_t choose_tile_bf16(int32_t n, int32_t r, int num_cus, int32_t preci
 }
 
 static int32_t choose_tile(int32_t n, int32_t r, int num_cus) {
-  // Preference from a tile sweep at N=2000, R=1024 on MI355X: 64x64 tiles
-  // (two workgroups per CU) with the 32x32x2 MFMA and 64-deep slabs lead.
+  // Preference from tile sweeps on MI355X: at N=2000, R=1024 the 8-wave
+  // direct-to-LDS tiles (64x128, 128x64) lead; a problem with at least four
+  // 64x128 tiles per CU (N=8000, R=2048) runs best on the register-staged
+  // 64x128 tile.
+  {
+    const TileShape big = tile_shape(1);
+    if ((round_up(n, big.bm) / big.bm) * (round_up(r, big.bn) / big.bn) >= 4 * (int64_t)num_cus)
+      return 1;
+  }
   const int32_t order[] = {27, 26, 2, 9, 12, 6, 3};
   int32_t best = 3;
   int64_t best_tiles = -1;

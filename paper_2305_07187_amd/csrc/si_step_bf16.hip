@@ -397,7 +397,8 @@ __device__ __forceinline__ void update_b(float q, float p, float f, float dt, fl
 template <class C, int ORDER, int WALL>
 __global__ __launch_bounds__(C::NT) void step_bf16_kernel(BStepArgs a) {
   __shared__ __attribute__((aligned(16))) uint16_t smem[C::LDS_ELEMS];
-  const int m0 = blockIdx.x * C::BM, n0 = blockIdx.y * C::BN;
+  const int t = xcd_tile(blockIdx.x, gridDim.x), ncol = a.r_pad / C::BN;
+  const int m0 = (t / ncol) * C::BM, n0 = (t % ncol) * C::BN;
   floatx16 acc[C::TM][C::TN];
   bf16_mainloop<C>(a, m0, n0, acc, smem);
 
@@ -451,27 +452,38 @@ __global__ __launch_bounds__(C::NT) void step_bf16_kernel(BStepArgs a) {
 template <class C, int ORDER, int WALL>
 __global__ __launch_bounds__(C::NT) void step_bf16_dma_kernel(BStepArgs a) {
   __shared__ __attribute__((aligned(16))) uint8_t smem[C::LDS_BYTES];
-  const int m0 = blockIdx.x * C::BM, n0 = blockIdx.y * C::BN;
+  const int t = xcd_tile(blockIdx.x, gridDim.x), ncol = a.r_pad / C::BN;
+  const int m0 = (t / ncol) * C::BM, n0 = (t % ncol) * C::BN;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wy = wave / C::WN, wx = wave % C::WN;
-  // state of this lane's outputs, loaded while the contraction runs
+  // State of this lane's outputs.  It is loaded before the contraction, so
+  // that its latency overlaps the matrix work, when the registers allow:
+  // for wave tiles of at most two MFMA blocks, or when a single four-wave
+  // group fills the CU's LDS (one wave per SIMD owns the whole register
+  // file).  Otherwise it is loaded afterwards (32 registers per block would
+  // stay live through the main loop).
+  constexpr bool PREFETCH = C::TM * C::TN <= 2 || (C::NW == 4 && C::LDS_BYTES > 80 * 1024);
   floatx4 q4[C::TM][4][C::TN], p4[C::TM][4][C::TN], h4[C::TM][4];
+  auto load_state = [&]() {
 #pragma unroll
-  for (int i = 0; i < C::TM; ++i)
+    for (int i = 0; i < C::TM; ++i)
 #pragma unroll
-    for (int g = 0; g < 4; ++g) {
-      const int row = m0 + wy * C::WTM + i * 32 + g * 8 + (lane / 32) * 4;
-      h4[i][g] = floatx4{0.f, 0.f, 0.f, 0.f};
-      if (a.h) h4[i][g] = *reinterpret_cast<const floatx4 *>(a.h + row);
+      for (int g = 0; g < 4; ++g) {
+        const int row = m0 + wy * C::WTM + i * 32 + g * 8 + (lane / 32) * 4;
+        h4[i][g] = floatx4{0.f, 0.f, 0.f, 0.f};
+        if (a.h) h4[i][g] = *reinterpret_cast<const floatx4 *>(a.h + row);
 #pragma unroll
-      for (int j = 0; j < C::TN; ++j) {
-        const size_t off = (size_t)(n0 + wx * C::WTN + j * 32 + (lane % 32)) * a.ld + row;
-        q4[i][g][j] = *reinterpret_cast<const floatx4 *>(a.q_in + off);
-        p4[i][g][j] = *reinterpret_cast<const floatx4 *>(a.p_in + off);
+        for (int j = 0; j < C::TN; ++j) {
+          const size_t off = (size_t)(n0 + wx * C::WTN + j * 32 + (lane % 32)) * a.ld + row;
+          q4[i][g][j] = *reinterpret_cast<const floatx4 *>(a.q_in + off);
+          p4[i][g][j] = *reinterpret_cast<const floatx4 *>(a.p_in + off);
+        }
       }
-    }
+  };
+  if constexpr (PREFETCH) load_state();
   floatx16 acc[C::TM][C::TN];
   bf16_mainloop_dma<C>(a, m0, n0, acc, smem);
+  if constexpr (!PREFETCH) load_state();
 
   const float dt = a.dt[a.t], zeta = a.zeta[a.t];
 #pragma unroll
@@ -516,7 +528,7 @@ __global__ __launch_bounds__(C::NT) void step_bf16_dma_kernel(BStepArgs a) {
 template <class C>
 static hipError_t launch_bd(const BStepArgs &a, hipStream_t s) {
   if (a.n_pad % C::BM || a.r_pad % C::BN || a.n_pad % C::BK) return hipErrorInvalidValue;
-  dim3 grid(a.n_pad / C::BM, a.r_pad / C::BN), block(C::NT);
+  dim3 grid((a.n_pad / C::BM) * (a.r_pad / C::BN)), block(C::NT);
   switch (a.order * 2 + a.wall) {
     case 0: step_bf16_dma_kernel<C, SI_ORDER_PAPER, SI_WALL_CLAMP><<<grid, block, 0, s>>>(a); break;
     case 1: step_bf16_dma_kernel<C, SI_ORDER_PAPER, SI_WALL_INELASTIC><<<grid, block, 0, s>>>(a); break;
@@ -543,7 +555,13 @@ static hipError_t launch_bd(const BStepArgs &a, hipStream_t s) {
   X(10, 64, 128, 2, 2, 64, 3)    \
   X(11, 128, 64, 2, 2, 64, 3)    \
   X(12, 128, 128, 2, 2, 64, 3)   \
-  X(13, 64, 64, 2, 2, 128, 4)
+  X(13, 64, 64, 2, 2, 128, 4)    \
+  X(14, 128, 128, 2, 2, 128, 3)  \
+  X(15, 128, 128, 2, 2, 64, 4)   \
+  X(16, 128, 256, 2, 4, 64, 3)   \
+  X(17, 256, 128, 4, 2, 64, 3)   \
+  X(18, 128, 128, 2, 4, 64, 3)   \
+  X(19, 128, 128, 4, 2, 128, 3)
 
 TileShape tile_shape_bf16(int32_t tile) {
   switch (tile) {
@@ -559,7 +577,7 @@ TileShape tile_shape_bf16(int32_t tile) {
 template <class C>
 static hipError_t launch_b(const BStepArgs &a, hipStream_t s) {
   if (a.n_pad % C::BM || a.r_pad % C::BN || a.n_pad % C::BK) return hipErrorInvalidValue;
-  dim3 grid(a.n_pad / C::BM, a.r_pad / C::BN), block(C::NT);
+  dim3 grid((a.n_pad / C::BM) * (a.r_pad / C::BN)), block(C::NT);
   switch (a.order * 2 + a.wall) {
     case 0: step_bf16_kernel<C, SI_ORDER_PAPER, SI_WALL_CLAMP><<<grid, block, 0, s>>>(a); break;
     case 1: step_bf16_kernel<C, SI_ORDER_PAPER, SI_WALL_INELASTIC><<<grid, block, 0, s>>>(a); break;

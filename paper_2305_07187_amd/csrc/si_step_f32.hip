@@ -122,8 +122,9 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, const float *__rest
 template <class C, int ORDER, int WALL>
 __global__ __launch_bounds__(C::NT) void step_f32_kernel(StepArgs a) {
   __shared__ __attribute__((aligned(16))) float smem[C::LDS_FLOATS];
-  step_tile<C, ORDER, WALL>(a, a.J, a.q_in, a.p_in, a.q_out, a.p_out, a.ld, blockIdx.x * C::BM,
-                            blockIdx.y * C::BN, smem);
+  const int t = xcd_tile(blockIdx.x, gridDim.x), ncol = a.r_pad / C::BN;
+  step_tile<C, ORDER, WALL>(a, a.J, a.q_in, a.p_in, a.q_out, a.p_out, a.ld, (t / ncol) * C::BM,
+                            (t % ncol) * C::BN, smem);
 }
 
 // Batched form: one launch advances every instance of a batch by one step.
@@ -194,7 +195,7 @@ TileShape tile_shape(int32_t tile) {
 template <class C>
 static hipError_t launch_cfg(const StepArgs &a, hipStream_t s) {
   if (a.n_pad % C::BM || a.r_pad % C::BN || a.n_pad % C::BK) return hipErrorInvalidValue;
-  dim3 grid(a.n_pad / C::BM, a.r_pad / C::BN), block(C::NT);
+  dim3 grid((a.n_pad / C::BM) * (a.r_pad / C::BN)), block(C::NT);
   const int sel = a.order * 2 + a.wall;
   switch (sel) {
     case 0: step_f32_kernel<C, SI_ORDER_PAPER, SI_WALL_CLAMP><<<grid, block, 0, s>>>(a); break;

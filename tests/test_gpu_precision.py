@@ -134,6 +134,37 @@ def test_fp8_and_bf16_j_identical():
     assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
 
 
+@pytest.mark.parametrize("precision,group", [
+    ("bf16x_bf16j", (7, 8, 9, 10, 11, 12, 13, 15, 16, 17, 18)),
+    ("bf16x_bf16j", (1, 2, 3, 4, 5, 6)),
+    ("bf16x_fp8j", (9, 13, 14, 19)),
+    ("bf16x_hiloj", (7, 8, 9, 10, 11, 12, 18)),
+    ("bf16x3_exactj", (7, 8, 11))])
+def test_bf16_tiles_agree(precision, group):
+    # Within one pipeline kind every tile shape feeds the same contraction
+    # indices to each MFMA and chains the MFMAs in the same order, so the
+    # trajectories agree bit for bit whatever the block, wave or slab shape.
+    import torch
+    announce(f"{precision} tiles agree {group}")
+    n, r, S = 256, 256, 40
+    J = instances.make_gauss(n, 8) if precision == "bf16x_hiloj" else instances.make_pm1(n, 8)
+    x0 = instances.make_x0(n, r, 8)
+    ref = None
+    for tile in group:
+        m = _model(J, x0, S, precision, tile=tile)
+        assert m.info()["tile"] == tile
+        m.run(S)
+        x, p, _ = m.state()
+        torch.cuda.synchronize()
+        cur = (x.cpu().numpy(), p.cpu().numpy())
+        name = m.info()["kernel_name"]
+        m.close()
+        if ref is None:
+            ref = cur
+        else:
+            assert np.array_equal(cur[0], ref[0]) and np.array_equal(cur[1], ref[1]), name
+
+
 def _runs(precision, cases, S, steps):
     import torch
     res = []
