@@ -121,6 +121,9 @@ typedef struct {
   int32_t graph_steps;      /* steps per captured HIP graph (0: not captured) */
   int64_t device_bytes;     /* device memory owned by the context */
   char kernel_name[64];     /* name of the step kernel in use */
+  int32_t resident_steps;   /* run() calls of at least this many steps use the
+                               resident launch (0: off or not available) */
+  int32_t resident_groups;  /* workgroups of that launch (0: not available) */
 } si_info;
 
 /* Fill *prm (host) with the paper's parameter values and total_steps = S. */
@@ -183,6 +186,22 @@ si_status spring_ising_run(si_ctx *ctx, int32_t n_steps);
  * and buffer parity; up to four are kept) and replayed as one graph launch.
  * Results are bit-identical to direct launches.  0 turns graphs off. */
 si_status spring_ising_set_graph(si_ctx *ctx, int32_t min_steps);
+
+/* Execute run() calls of at least min_steps steps as one resident launch
+ * (FP32 single instance; the per-step loop of Eq. 8 moved onto the device):
+ * every workgroup owns one output tile for the whole call and keeps that
+ * tile's q and p in registers, only q (which every other tile's coupling
+ * product reads) passes through memory, and a grid-wide barrier separates
+ * consecutive steps.  Used only when all workgroups of the step kernel in
+ * use fit on the device at once (cooperative launch); otherwise run()
+ * launches per step.  Results are bit-identical to per-step launches.  A
+ * resident run() returns after the launch has completed, having checked the
+ * barrier's time-out flag: a barrier that does not open within about 2 s
+ * ends the launch and poisons the context (SI_ERR_HIP).  The barrier costs
+ * about as much as a kernel launch, so the resident form pays off only for
+ * small, launch-bound problems (a few dozen workgroups).  0 (the default)
+ * turns it off.  SI_ERR_INVALID if min_steps < 0. */
+si_status spring_ising_set_resident(si_ctx *ctx, int32_t min_steps);
 
 /* Autotuner: time `steps` steps of every step kernel that can serve this
  * context (its precision and padded shape), starting from the current state,

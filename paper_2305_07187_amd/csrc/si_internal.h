@@ -54,6 +54,25 @@ struct StepArgs {
 
 hipError_t launch_step_f32(int32_t tile, const StepArgs &a, hipStream_t s);
 
+// Resident form: one cooperative launch runs n_steps steps.  Every workgroup
+// owns one output tile for the whole launch and keeps that tile's q and p in
+// registers; only q, which every other tile's product needs, goes to memory
+// (the two q buffers alternate), and a grid-wide barrier separates the
+// steps.  p reaches p[cur at exit] after the last step.
+struct ResidentArgs {
+  float *q[2];
+  float *p[2];
+  int32_t cur;        // buffer index holding the state at entry
+  int32_t n_steps;
+  uint32_t *count;    // per-group count of completed steps [groups]; zero at launch
+  int32_t *err;       // set to 1 when a barrier wait times out
+};
+// Workgroups of tile `tile` that fit on one CU at once (0: no resident form
+// for this tile).
+hipError_t resident_f32_groups_per_cu(int32_t tile, int32_t order, int32_t wall, int *groups);
+hipError_t launch_resident_f32(int32_t tile, const StepArgs &a, const ResidentArgs &r,
+                               hipStream_t s);
+
 // Batched form: per-instance buffers and the work list of one grouped launch.
 constexpr int BATCH_BM = 64, BATCH_BN = 64;
 struct BatchDesc {

@@ -116,6 +116,11 @@ struct si_ctx {
   };
   std::vector<GraphEntry> graphs;
   int32_t graph_min_steps = 0;  // 0: graphs off
+  // resident launches of run(n): n >= resident_min_steps (0: off)
+  int32_t resident_min_steps = 0;
+  int32_t resident_tile = -1, resident_per_cu = 0;  // occupancy cache for `tile`
+  int32_t *res_sync = nullptr;  // [0] time-out flag, [64 ..] per-group step counts
+  int32_t res_sync_cap = 0;
   hipStream_t cap_stream = nullptr;
   // in-run best state per replica
   double *best_e = nullptr, *e_scratch = nullptr;
@@ -782,14 +787,74 @@ static si_status run_graph(si_ctx *c, int32_t n_steps) {
   return SI_OK;
 }
 
+// Workgroups of the resident launch for the current tile, or 0 when the
+// context has no resident form or they do not all fit on the device.
+static int32_t resident_groups(si_ctx *c) {
+  if (c->n_inst || c->qplanes) return 0;
+  if (c->resident_tile != c->tile) {
+    int per = 0;
+    if (resident_f32_groups_per_cu(c->tile, c->prm.order, c->prm.wall, &per) != hipSuccess)
+      per = 0;
+    (void)hipGetLastError();
+    c->resident_tile = c->tile;
+    c->resident_per_cu = per;
+  }
+  const TileShape ts = tile_shape(c->tile);
+  const int64_t groups = (int64_t)(c->n_pad / ts.bm) * (c->r_pad / ts.bn);
+  if (c->resident_per_cu <= 0 || groups > (int64_t)c->resident_per_cu * c->num_cus) return 0;
+  return (int32_t)groups;
+}
+
+static si_status run_resident(si_ctx *c, int32_t n_steps, int32_t groups) {
+  // res_sync: [0] time-out flag, [64 ..] one completed-step count per group
+  if (c->res_sync_cap < groups) {
+    SI_HIP(c, c->alloc(&c->res_sync, 64 + (int64_t)groups));
+    c->res_sync_cap = groups;
+  }
+  SI_HIP(c, launch_zero_i32(c->res_sync, 64 + (int64_t)groups, c->stream));
+  StepArgs a = step_args(c);
+  a.t = c->t;
+  ResidentArgs r;
+  r.q[0] = c->q[0];
+  r.q[1] = c->q[1];
+  r.p[0] = c->p[0];
+  r.p[1] = c->p[1];
+  r.cur = c->cur;
+  r.n_steps = n_steps;
+  r.count = reinterpret_cast<uint32_t *>(c->res_sync + 64);
+  r.err = c->res_sync;
+  SI_HIP(c, launch_resident_f32(c->tile, a, r, c->stream));
+  c->t += n_steps;
+  c->cur ^= (n_steps & 1);
+  int32_t err = 0;
+  SI_HIP(c, hipMemcpyAsync(&err, c->res_sync, sizeof err, hipMemcpyDeviceToHost, c->stream));
+  SI_HIP(c, hipStreamSynchronize(c->stream));
+  if (err) {
+    c->poisoned = true;
+    return fail(SI_ERR_HIP, "run: a grid barrier of the resident launch timed out");
+  }
+  return SI_OK;
+}
+
 si_status spring_ising_run(si_ctx *c, int32_t n_steps) {
   SI_USABLE(c);
   if (n_steps < 0) return fail(SI_ERR_INVALID, "run: n_steps=%d < 0", n_steps);
   if ((int64_t)c->t + n_steps > c->prm.total_steps)
     return fail(SI_ERR_RANGE, "run: t=%d + n_steps=%d exceeds total_steps=%d", c->t, n_steps,
                 c->prm.total_steps);
+  if (c->resident_min_steps > 0 && n_steps >= c->resident_min_steps && n_steps > 1) {
+    const int32_t groups = resident_groups(c);
+    if (groups > 0) return run_resident(c, n_steps, groups);
+  }
   if (c->graph_min_steps > 0 && n_steps >= c->graph_min_steps) return run_graph(c, n_steps);
   return do_steps(c, n_steps);
+}
+
+si_status spring_ising_set_resident(si_ctx *c, int32_t min_steps) {
+  SI_USABLE(c);
+  if (min_steps < 0) return fail(SI_ERR_INVALID, "set_resident: min_steps < 0");
+  c->resident_min_steps = min_steps;
+  return SI_OK;
 }
 
 si_status spring_ising_set_graph(si_ctx *c, int32_t min_steps) {
@@ -1083,6 +1148,8 @@ si_status spring_ising_info(si_ctx *c, si_info *info) {
   info->precision = c->prm.precision;
   info->graph_steps = c->graph_min_steps;
   info->device_bytes = c->bytes;
+  info->resident_groups = c->poisoned ? 0 : resident_groups(c);
+  info->resident_steps = info->resident_groups ? c->resident_min_steps : 0;
   if (c->n_inst)
     snprintf(info->kernel_name, sizeof info->kernel_name, "step_batch_f32_%dx%d_x%d", BATCH_BM,
              BATCH_BN, c->n_inst);

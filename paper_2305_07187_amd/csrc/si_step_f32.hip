@@ -127,6 +127,120 @@ __global__ __launch_bounds__(C::NT) void step_f32_kernel(StepArgs a) {
                             (t % ncol) * C::BN, smem);
 }
 
+// Grid-wide barrier of a resident launch, without atomic read-modify-write:
+// group g publishes the number of steps it has completed in flags[g] (a
+// release store, which also writes this XCD's L2 back), and the first wave
+// of every group polls all the flags, one per lane, with plain loads until
+// each has reached `step`.  A single acquire fence per group then
+// invalidates the stale lines before the next step reads q.  The wait is
+// bounded (about 2 s of the 100 MHz real-time counter, and at most 2^26
+// polls): a barrier that cannot complete sets *err and every group leaves
+// instead of hanging.
+__device__ __forceinline__ bool grid_barrier(uint32_t *flags, uint32_t step, int32_t *err) {
+  __shared__ int32_t pass;
+  const int groups = gridDim.x;
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  __syncthreads();
+  if (threadIdx.x == 0)
+    __hip_atomic_store(flags + blockIdx.x, step, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  if (threadIdx.x < 64) {
+    const int lane = threadIdx.x;
+    const uint64_t start = __builtin_amdgcn_s_memrealtime();
+    int32_t ok = 1;
+    uint32_t polls = 0;
+    for (;;) {
+      bool ready = true;
+      for (int g = lane; g < groups; g += 64)
+        ready &= __hip_atomic_load(flags + g, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= step;
+      if (__all(ready)) break;
+      if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+        ok = 0;
+        break;
+      }
+      if (__builtin_amdgcn_s_memrealtime() - start > 200000000ull || ++polls > (1u << 26)) {
+        if (lane == 0) __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        ok = 0;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    if (lane == 0) pass = ok;
+  }
+  __syncthreads();
+  return pass != 0;
+}
+
+template <class C, int ORDER, int WALL>
+__global__ __launch_bounds__(C::NT) void resident_f32_kernel(StepArgs a, ResidentArgs r) {
+  __shared__ __attribute__((aligned(16))) float smem[C::LDS_FLOATS];
+  const int groups = gridDim.x;
+  const int t = xcd_tile(blockIdx.x, groups), ncol = a.r_pad / C::BN;
+  const int m0 = (t / ncol) * C::BM, n0 = (t % ncol) * C::BN;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int wy = wave / C::WN, wx = wave % C::WN;
+  constexpr int G = C::M::NACC / 4;
+  const int ld = a.ld;
+  floatx4 q4[C::TM][G][C::TN], p4[C::TM][G][C::TN], h4[C::TM][G];
+  int cur = r.cur;
+#pragma unroll
+  for (int i = 0; i < C::TM; ++i)
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      const int row = m0 + wy * C::WTM + i * C::MB + g * 8 + (lane / C::MB) * 4;
+      h4[i][g] = floatx4{0.f, 0.f, 0.f, 0.f};
+      if (a.h) h4[i][g] = *reinterpret_cast<const floatx4 *>(a.h + row);
+#pragma unroll
+      for (int j = 0; j < C::TN; ++j) {
+        const size_t off = (size_t)(n0 + wx * C::WTN + j * C::MB + (lane % C::MB)) * ld + row;
+        q4[i][g][j] = *reinterpret_cast<const floatx4 *>(r.q[cur] + off);
+        p4[i][g][j] = *reinterpret_cast<const floatx4 *>(r.p[cur] + off);
+      }
+    }
+  for (int s = 0; s < r.n_steps; ++s) {
+    typename C::acc_t acc[C::TM][C::TN];
+    if constexpr (C::STAGES > 0)
+      f32_mainloop_dma<C>(a.J, r.q[cur], ld, ld, m0, n0, acc, smem);
+    else
+      f32_mainloop<C, B_PLAIN>(a.J, r.q[cur], ld, ld, m0, n0, acc, smem);
+    const float dt = a.dt[a.t + s], zeta = a.zeta[a.t + s];
+    float *qd = r.q[cur ^ 1];
+#pragma unroll
+    for (int i = 0; i < C::TM; ++i)
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        const int row = m0 + wy * C::WTM + i * C::MB + g * 8 + (lane / C::MB) * 4;
+#pragma unroll
+        for (int j = 0; j < C::TN; ++j) {
+          const size_t off = (size_t)(n0 + wx * C::WTN + j * C::MB + (lane % C::MB)) * ld + row;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            float qv, pv;
+            update<ORDER, WALL>(q4[i][g][j][v], p4[i][g][j][v], acc[i][j][4 * g + v] + h4[i][g][v],
+                                dt, zeta, a.k, a.inv_m, a.qmax, a.pmax, qv, pv);
+            q4[i][g][j][v] = qv;
+            p4[i][g][j][v] = pv;
+          }
+          *reinterpret_cast<floatx4 *>(qd + off) = q4[i][g][j];
+        }
+      }
+    cur ^= 1;
+    if (s + 1 < r.n_steps && !grid_barrier(r.count, (uint32_t)(s + 1), r.err)) return;
+  }
+#pragma unroll
+  for (int i = 0; i < C::TM; ++i)
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      const int row = m0 + wy * C::WTM + i * C::MB + g * 8 + (lane / C::MB) * 4;
+#pragma unroll
+      for (int j = 0; j < C::TN; ++j) {
+        const size_t off = (size_t)(n0 + wx * C::WTN + j * C::MB + (lane % C::MB)) * ld + row;
+        *reinterpret_cast<floatx4 *>(r.p[cur] + off) = p4[i][g][j];
+      }
+    }
+}
+
 // Batched form: one launch advances every instance of a batch by one step.
 // Work item w = (instance, row tile, column tile); items are ordered by
 // decreasing contraction length so the longest tiles start first.
@@ -205,6 +319,68 @@ static hipError_t launch_cfg(const StepArgs &a, hipStream_t s) {
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+template <class C>
+static const void *resident_kernel(int order, int wall) {
+  switch (order * 2 + wall) {
+    case 0: return reinterpret_cast<const void *>(&resident_f32_kernel<C, SI_ORDER_PAPER, SI_WALL_CLAMP>);
+    case 1: return reinterpret_cast<const void *>(&resident_f32_kernel<C, SI_ORDER_PAPER, SI_WALL_INELASTIC>);
+    case 2: return reinterpret_cast<const void *>(&resident_f32_kernel<C, SI_ORDER_SYMPLECTIC, SI_WALL_CLAMP>);
+    case 3: return reinterpret_cast<const void *>(&resident_f32_kernel<C, SI_ORDER_SYMPLECTIC, SI_WALL_INELASTIC>);
+    default: return nullptr;
+  }
+}
+
+template <class C>
+static hipError_t resident_groups(int order, int wall, int *groups) {
+  const void *k = resident_kernel<C>(order, wall);
+  if (!k) return hipErrorInvalidValue;
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(groups, k, C::NT, 0);
+}
+
+template <class C>
+static hipError_t resident_launch(const StepArgs &a, const ResidentArgs &r, hipStream_t s) {
+  if (a.n_pad % C::BM || a.r_pad % C::BN || a.n_pad % C::BK) return hipErrorInvalidValue;
+  const void *k = resident_kernel<C>(a.order, a.wall);
+  if (!k) return hipErrorInvalidValue;
+  StepArgs aa = a;
+  ResidentArgs rr = r;
+  void *args[] = {&aa, &rr};
+  return hipLaunchCooperativeKernel(k, dim3((a.n_pad / C::BM) * (a.r_pad / C::BN)), dim3(C::NT),
+                                    args, 0, s);
+}
+
+// Tiles with a resident form: the automatic choices of the FP32 path.
+#define SI_HAS_RESIDENT(id) ((id) == 27 || (id) == 26 || (id) == 2 || (id) == 1 || (id) == 3)
+hipError_t resident_f32_groups_per_cu(int32_t tile, int32_t order, int32_t wall, int *groups) {
+  *groups = 0;
+  switch (tile) {
+#define SI_RES_Q(id, bm, bn, wm, wn, mb, bk, st, ks)                                  \
+  case id:                                                                           \
+    if constexpr (SI_HAS_RESIDENT(id))                                               \
+      return resident_groups<F32Cfg<bm, bn, wm, wn, mb, bk, st, ks>>(order, wall, groups); \
+    else                                                                             \
+      return hipSuccess;
+    SI_F32_TILES(SI_RES_Q)
+#undef SI_RES_Q
+    default: return hipSuccess;
+  }
+}
+
+hipError_t launch_resident_f32(int32_t tile, const StepArgs &a, const ResidentArgs &r,
+                               hipStream_t s) {
+  switch (tile) {
+#define SI_RES_L(id, bm, bn, wm, wn, mb, bk, st, ks)                    \
+  case id:                                                             \
+    if constexpr (SI_HAS_RESIDENT(id))                                 \
+      return resident_launch<F32Cfg<bm, bn, wm, wn, mb, bk, st, ks>>(a, r, s); \
+    else                                                               \
+      return hipErrorInvalidValue;
+    SI_F32_TILES(SI_RES_L)
+#undef SI_RES_L
+    default: return hipErrorInvalidValue;
+  }
 }
 
 // Batched tiles: 64 x 64, 32x32x2 MFMA, direct-to-LDS ring (4 stages).

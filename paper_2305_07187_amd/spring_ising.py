@@ -53,6 +53,7 @@ class si_info(ctypes.Structure):
         ("j_bf16_exact", ctypes.c_int32), ("tile", ctypes.c_int32),
         ("precision", ctypes.c_int32), ("graph_steps", ctypes.c_int32),
         ("device_bytes", ctypes.c_int64), ("kernel_name", ctypes.c_char * 64),
+        ("resident_steps", ctypes.c_int32), ("resident_groups", ctypes.c_int32),
     ]
 
     def as_dict(self):
@@ -87,6 +88,7 @@ _SIGNATURES = {
     "spring_ising_info": [_P, ctypes.POINTER(si_info)],
     "spring_ising_relaxed_energy_grad": [_P, _I, _P, _P, _P],
     "spring_ising_set_graph": [_P, _I],
+    "spring_ising_set_resident": [_P, _I],
     "spring_ising_update_best": [_P],
     "spring_ising_get_best": [_P, _P, _P],
     "spring_ising_hamiltonian": [_P, _P],
@@ -266,6 +268,10 @@ def spring_ising_hamiltonian(ctx, H):
 
 def spring_ising_set_graph(ctx, min_steps):
     _check(load_library().spring_ising_set_graph(ctx, int(min_steps)))
+
+
+def spring_ising_set_resident(ctx, min_steps):
+    _check(load_library().spring_ising_set_resident(ctx, int(min_steps)))
 
 
 def spring_ising_autotune(ctx, steps):
@@ -470,6 +476,9 @@ class SpringIsing:
 
     def set_graph(self, min_steps):
         spring_ising_set_graph(self.ctx, min_steps)
+
+    def set_resident(self, min_steps):
+        spring_ising_set_resident(self.ctx, min_steps)
 
     def autotune(self, steps=20):
         return spring_ising_autotune(self.ctx, steps)
