@@ -39,12 +39,16 @@ PEAK_FP32_MFMA_TFLOPS = 157.3
 PEAK_BF16_MFMA_TFLOPS = 2500.0
 PEAK_HBM_GBS = 8000.0
 FORMS = ["bf16x_fp8j", "bf16x_bf16j", "bf16x3_exactj"]
-# HBM/MALL bytes per launch of a step kernel at this workload, from two
-# rocprofv3 counter passes (FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000; the
-# factors come from an elementwise kernel of known size in the same runs).
-# Keyed by kernel name; an entry is removed whenever that kernel changes.
+# HBM/MALL bytes per launch of a step kernel, from two rocprofv3 counter
+# passes (FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000; the factors come from an
+# elementwise kernel of known size in the same runs).  Keyed by (kernel,
+# precision, N, R); an entry is removed whenever that kernel's code changes.
 MEASURED_TRAFFIC_BYTES = {
-    "step_f32_64x64_w2x2_mfma32_k32_s0_a1": 114.67e6,
+    ("step_f32_64x128_w2x4_mfma32_k32_s4_a1", "fp32", 2000, 1024): 114.62e6,
+    ("step_bf16_64x64_w2x2_k128_s3", "bf16x_fp8j", 2000, 1024): 75.60e6,
+    ("step_bf16_64x64_w2x2_k64_s4", "bf16x_bf16j", 2000, 1024): 79.77e6,
+    ("step_bf16_128x128_w2x2_k128_s3", "bf16x_fp8j", 2000, 2048): 157.39e6,
+    ("step_bf16_128x128_w2x4_k64_s3", "bf16x_hiloj", 8000, 2048): 1970.76e6,
 }
 
 
@@ -79,6 +83,7 @@ def cpu_baseline(budget_s: float = 15.0):
 
 
 def timed_runs(model, x0, iters, steps, warmup, stream):
+    exact = bool(model.info()["j_integer"])
     """Full runs (reset, iters steps, energy); per-run HIP events bracket the
     step launches.  Returns (elapsed_s, per-launch us, last energies)."""
     import torch
@@ -90,7 +95,7 @@ def timed_runs(model, x0, iters, steps, warmup, stream):
         model.run(iters)
         if ev is not None:
             ev[1].record(stream)
-        return model.energy()
+        return model.energy(exact=exact)
 
     for _ in range(warmup):
         one_run()
@@ -134,6 +139,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the precision-form lines")
     ap.add_argument("--iters", type=int, default=ITERS, help=argparse.SUPPRESS)
+    # other shapes, for profiling the precision configurations (not bench lines)
+    ap.add_argument("--n", type=int, default=N, help=argparse.SUPPRESS)
+    ap.add_argument("--replicas", type=int, default=R, help=argparse.SUPPRESS)
+    ap.add_argument("--couplings", default="pm1", choices=["pm1", "gauss"], help=argparse.SUPPRESS)
     ap.add_argument("--tile", type=int, default=0, help="step-kernel tile id (0 = automatic)")
     ap.add_argument("--precision", default="fp32", help="fp32 | bf16x_fp8j | bf16x_bf16j | "
                     "bf16x_hiloj | bf16x3_exactj (the headline line is fp32)")
@@ -165,24 +174,26 @@ def main():
         torch.mul(src, 2.0, out=dst)
         torch.cuda.synchronize()
         del src, dst
-    Jn = instances.make_pm1(N, 0)
-    J = torch.from_numpy(Jn).to(dev)
-    x0 = torch.from_numpy(instances.make_x0(N, R, 0)).to(dev)
+    n, r = args.n, args.replicas
+    J = instances.make_J_torch(n, args.couplings, 0, device=dev)
+    x0 = instances.make_x0_torch(n, r, 0, device=dev)
     stream = torch.cuda.current_stream()
-    W = float(-np.triu(Jn.astype(np.float64), 1).sum())
+    W = float(-torch.triu(J.double(), 1).sum())
 
     model = si.SpringIsing(J, x0, total_steps=iters, tile=args.tile, precision=args.precision)
     info = model.info()
+    kind = ("K2000-shaped +-1" if (n, args.couplings) == (2000, "pm1")
+            else {"pm1": "+-1", "gauss": "Gaussian N(0,1)"}[args.couplings])
     elapsed, kernel_us, energies = timed_runs(model, x0, iters, args.steps, args.warmup, stream)
     e = energies.cpu().numpy().astype(np.float64)
     cuts = (W - e) / 2
-    flops = 2.0 * N * N * R
+    flops = 2.0 * n * n * r
     achieved = flops / (kernel_us * 1e-6) / 1e12
-    value = N * R * iters * args.steps / elapsed
+    value = n * r * iters * args.steps / elapsed
     fp32_line = args.precision == "fp32"
     peak = PEAK_FP32_MFMA_TFLOPS if fp32_line else PEAK_BF16_MFMA_TFLOPS
     out = {
-        "metric": "spin-updates/s (N*R*steps/s) at N=2000",
+        "metric": f"spin-updates/s (N*R*steps/s) at N={n}",
         "value": value,
         "unit": "spin-updates/s",
         "n_gpus": 1,
@@ -194,24 +205,24 @@ def main():
         "vs_baseline": None,
         "dtype": "f32" if fp32_line else "bf16",
         "data": "synthetic",
-        "config": {"workload": f"K2000-shaped +-1 complete graph, N={N}, R={R} replicas, "
+        "config": {"workload": f"{kind} complete graph, N={n}, R={r} replicas, "
                                f"{iters} iterations, paper linear zeta schedule, "
                                f"{args.precision}",
-                   "n": N, "replicas": R, "iterations": iters, "precision": args.precision,
+                   "n": n, "replicas": r, "iterations": iters, "precision": args.precision,
                    "kernel": info["kernel_name"]},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak,
-                     "traffic": MEASURED_TRAFFIC_BYTES.get(info["kernel_name"]),
+                     "traffic": MEASURED_TRAFFIC_BYTES.get((info["kernel_name"], args.precision, n, r)),
                      "traffic_unit": "bytes per launch",
                      "kernel": info["kernel_name"], "avg_launch_us": kernel_us,
                      "algorithmic_flop_per_launch": flops},
         "result": {"best_cut": float(cuts.max()), "mean_cut": float(cuts.mean()),
-                   "best_energy": int(e.min()), "mean_energy": float(e.mean())},
+                   "best_energy": float(e.min()), "mean_energy": float(e.mean())},
     }
 
-    if fp32_line and not args.no_forms and iters % CHECK_EVERY == 0:
+    if fp32_line and not args.no_forms and iters % CHECK_EVERY == 0 and args.couplings == "pm1":
         from scipy.stats import ks_2samp
-        target = float(np.sort(e)[max(0, int(0.01 * R) - 1)])  # 1% quantile (10th best)
+        target = float(np.sort(e)[max(0, int(0.01 * r) - 1)])  # 1% quantile (10th best)
         forms = {}
         for name in ["fp32"] + FORMS:
             m = model if name == "fp32" else si.SpringIsing(J, x0, total_steps=iters,
@@ -224,7 +235,7 @@ def main():
             Ec, times = run_with_checks(si, m, x0, iters, CHECK_EVERY, stream)
             hit = np.nonzero(Ec.min(axis=1) <= target)[0]
             frac_at_end = float((en <= target).mean())
-            rec = {"spin_updates_per_s": N * R * iters / el, "avg_launch_us": us,
+            rec = {"spin_updates_per_s": n * r * iters / el, "avg_launch_us": us,
                    "kernel": m.info()["kernel_name"],
                    "ttt_s": float(times[hit[0]]) / 1000.0 if len(hit) else None,
                    "ttt_step": int((hit[0] + 1) * CHECK_EVERY) if len(hit) else None,
@@ -233,7 +244,7 @@ def main():
             if name != "fp32":
                 rec["ks_pvalue_vs_fp32"] = float(ks_2samp(en, e).pvalue)
                 rec["mean_diff_in_se"] = float((en.mean() - e.mean()) /
-                                               np.sqrt(en.var() / R + e.var() / R))
+                                               np.sqrt(en.var() / r + e.var() / r))
                 m.close()
             forms[name] = rec
         t32 = forms["fp32"]["ttt_s"]
