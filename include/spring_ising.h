@@ -77,13 +77,17 @@ typedef enum { SI_WALL_CLAMP = 0, SI_WALL_INELASTIC = 1 } si_wall;
  *                 three BF16 pieces whose sum is the FP32 value exactly, so
  *                 every product is exact and only the FP32 accumulation
  *                 rounds (FP32-equivalent, on the BF16 matrix cores).
+ *   BF16X_MIXEDJ: per instance, BF16X_FP8J when J is exact in FP8 e4m3 and
+ *                 BF16X_HILOJ otherwise; spring_ising_info reports the form
+ *                 chosen for a single instance.
  * The master positions and momenta are FP32 in every mode. */
 typedef enum {
   SI_PREC_FP32 = 0,
   SI_PREC_BF16X_FP8J = 1,
   SI_PREC_BF16X_BF16J = 2,
   SI_PREC_BF16X_HILOJ = 3,
-  SI_PREC_BF16X3_EXACTJ = 4
+  SI_PREC_BF16X3_EXACTJ = 4,
+  SI_PREC_BF16X_MIXEDJ = 5
 } si_precision;
 
 /* Scalar parameters.  spring_ising_default_params() fills the paper's values:
@@ -153,7 +157,13 @@ si_status spring_ising_init(si_ctx **out, int32_t n, int32_t r, const float *J,
  *       symmetric zero-diagonal matrix.
  *   x0: host array of n_inst device pointers, instance i r*n[i] floats;
  *       initial momenta are 0.
- * FP32 only (other precisions: SI_ERR_UNSUPPORTED).  In every later call the
+ * Precisions: FP32 (64x64 tiles, instances padded to 64), or the BF16 forms
+ * BF16X_FP8J (every J exact in FP8), BF16X_HILOJ and BF16X_MIXEDJ (FP8 J
+ * where exact, hi + lo BF16 J otherwise), on 64x64 tiles with instances
+ * padded to 128; BF16X_BF16J and BF16X3_EXACTJ: SI_ERR_UNSUPPORTED.  Each
+ * instance's trajectory equals the single-instance run of the same form on
+ * the 64x64 tile of that shape (FP32: tile 14; FP8 J: BF16 tile 9; hi + lo:
+ * BF16 tile 7) bit for bit.  In every later call the
  * instances are concatenated: state/spin arrays hold instance i's r*n[i]
  * values (replica-major) at offset r * (n[0] + ... + n[i-1]); energies hold
  * instance i's r values at offset r*i.  set_field and

@@ -100,6 +100,19 @@ struct BStepArgs {
   int32_t order, wall;
 };
 hipError_t launch_step_bf16(int32_t tile, int32_t precision, const BStepArgs &a, hipStream_t s);
+// Batched precision form: per-instance J format (fmt 1: FP8 e4m3, 2: hi + lo
+// BF16), BF16 plane of q per instance; instances padded to 128 (FP8 slabs
+// are 128 deep).  `base` carries the schedules, constants and r_pad.
+constexpr int BATCH_BF16_NPAD = 128;
+struct BBatchDesc {
+  const void *Ja, *Jb;
+  float *q[2], *p[2];
+  uint16_t *qb[2];
+  int32_t n_pad, fmt;
+};
+hipError_t launch_step_batch_bf16(const BStepArgs &base, const BBatchDesc *descs,
+                                  const int4 *items, int32_t n_items, int32_t cur,
+                                  hipStream_t s);
 bool tile_valid_bf16(int32_t tile, int32_t precision);
 hipError_t launch_pack_j_lowp(const float *J, int64_t total, int32_t precision, void *out_a,
                               void *out_b, hipStream_t s);

@@ -108,6 +108,12 @@ struct si_ctx {
   int4 *b_items = nullptr;
   int32_t b_max_npad = 0;
   int64_t b_total_n = 0;
+  // batched precision form: per-instance J format (1: FP8, 2: hi + lo BF16)
+  bool b_lowp = false;
+  std::vector<int32_t> b_fmt;
+  std::vector<uint16_t *> b_qb[2];
+  std::vector<BBatchDesc> bb_desc_host;
+  BBatchDesc *bb_desc = nullptr;
   // captured HIP graphs of run(n) launch sequences, keyed by (t0, n, cur)
   struct GraphEntry {
     int32_t t0, n, cur;
@@ -190,7 +196,7 @@ static si_status check_params(const si_params *p) {
     return fail(SI_ERR_INVALID, "params: unknown order %d", p->order);
   if (p->wall != SI_WALL_CLAMP && p->wall != SI_WALL_INELASTIC)
     return fail(SI_ERR_INVALID, "params: unknown wall %d", p->wall);
-  if (p->precision < SI_PREC_FP32 || p->precision > SI_PREC_BF16X3_EXACTJ)
+  if (p->precision < SI_PREC_FP32 || p->precision > SI_PREC_BF16X_MIXEDJ)
     return fail(SI_ERR_INVALID, "params: unknown precision %d", p->precision);
   const int32_t last = p->precision == SI_PREC_FP32 ? TILE_F32_LAST : TILE_BF16_LAST;
   if (p->tile < 0 || p->tile > last)
@@ -318,19 +324,6 @@ si_status spring_ising_init(si_ctx **out, int32_t n, int32_t r, const float *J, 
   INIT_HIP(hipGetDevice(&c->device));
   INIT_HIP(hipDeviceGetAttribute(&c->num_cus, hipDeviceAttributeMultiprocessorCount, c->device));
 
-  const bool lowp = prm->precision != SI_PREC_FP32;
-  c->tile = prm->tile ? prm->tile
-                      : (lowp ? choose_tile_bf16(n, r, c->num_cus, prm->precision)
-                              : choose_tile(n, r, c->num_cus));
-  if (lowp && !tile_valid_bf16(c->tile, prm->precision)) {
-    const int32_t bad = c->tile;
-    delete c;
-    return fail(SI_ERR_INVALID, "init: tile %d cannot run precision %d", bad, prm->precision);
-  }
-  const TileShape ts = shape_of(prm->precision, c->tile);
-  c->n_pad = (int32_t)round_up(n, ts.bm > 128 ? ts.bm : 128);
-  c->r_pad = (int32_t)round_up(r, ts.bn > 64 ? ts.bn : 64);
-
   // validation of J: one host round trip
   INIT_HIP(c->alloc(&c->flags, 8));
   INIT_HIP(launch_zero_i32(c->flags, 8, c->stream));
@@ -344,6 +337,22 @@ si_status spring_ising_init(si_ctx **out, int32_t n, int32_t r, const float *J, 
     return fail(SI_ERR_INVALID, "init: J must be finite, symmetric with a zero diagonal "
                 "(asymmetric=%d nonzero_diagonal=%d nonfinite=%d)", a, d, f);
   }
+  if (c->prm.precision == SI_PREC_BF16X_MIXEDJ)
+    c->prm.precision = c->hflags[4] == 0 ? SI_PREC_BF16X_FP8J : SI_PREC_BF16X_HILOJ;
+  prm = &c->prm;
+
+  const bool lowp = prm->precision != SI_PREC_FP32;
+  c->tile = prm->tile ? prm->tile
+                      : (lowp ? choose_tile_bf16(n, r, c->num_cus, prm->precision)
+                              : choose_tile(n, r, c->num_cus));
+  if (lowp && !tile_valid_bf16(c->tile, prm->precision)) {
+    const int32_t bad = c->tile;
+    delete c;
+    return fail(SI_ERR_INVALID, "init: tile %d cannot run precision %d", bad, prm->precision);
+  }
+  const TileShape ts = shape_of(prm->precision, c->tile);
+  c->n_pad = (int32_t)round_up(n, ts.bm > 128 ? ts.bm : 128);
+  c->r_pad = (int32_t)round_up(r, ts.bn > 64 ? ts.bn : 64);
   const bool j_integer = c->hflags[3] == 0;
   const bool need_bf16 = prm->precision == SI_PREC_BF16X_BF16J ||
                          prm->precision == SI_PREC_BF16X3_EXACTJ;
@@ -403,8 +412,10 @@ si_status spring_ising_init_batch(si_ctx **out, int32_t n_inst, const int32_t *n
   if (r > (1 << 20)) return fail(SI_ERR_INVALID, "init_batch: r=%d too large", r);
   si_status st = check_params(prm);
   if (st != SI_OK) return st;
-  if (prm->precision != SI_PREC_FP32)
-    return fail(SI_ERR_UNSUPPORTED, "init_batch: the batched form runs in FP32");
+  if (prm->precision == SI_PREC_BF16X_BF16J || prm->precision == SI_PREC_BF16X3_EXACTJ)
+    return fail(SI_ERR_UNSUPPORTED, "init_batch: precision %d has no batched form", prm->precision);
+  if (prm->tile != 0) return fail(SI_ERR_INVALID, "init_batch: the batch uses fixed 64x64 tiles");
+  const bool lowp = prm->precision != SI_PREC_FP32;
   for (int32_t i = 0; i < n_inst; ++i) {
     if (n[i] < 1 || n[i] > 65536) return fail(SI_ERR_INVALID, "init_batch: n[%d]=%d", i, n[i]);
     if (!is_device_ptr(J[i]) || !is_device_ptr(x0[i]))
@@ -418,6 +429,7 @@ si_status spring_ising_init_batch(si_ctx **out, int32_t n_inst, const int32_t *n
   c->r = r;
   c->r_pad = (int32_t)round_up(r, BATCH_BN);
   c->tile = 0;
+  c->b_lowp = lowp;
 #define BINIT_HIP(expr)                                                                  \
   do {                                                                                   \
     hipError_t _e = (expr);                                                              \
@@ -438,19 +450,33 @@ si_status spring_ising_init_batch(si_ctx **out, int32_t n_inst, const int32_t *n
   BINIT_HIP(hipMemcpyAsync(hfl.data(), flags, hfl.size() * sizeof(int32_t), hipMemcpyDeviceToHost,
                            c->stream));
   BINIT_HIP(hipStreamSynchronize(c->stream));
-  int64_t jtot = 0, j8tot = 0, stot = 0, xoff = 0;
+  int64_t jtot = 0, j8tot = 0, stot = 0, xoff = 0, latot = 0, lbtot = 0;
   c->b_n.resize(n_inst);
   c->b_npad.resize(n_inst);
   c->b_jmax.resize(n_inst);
   c->b_xoff.resize(n_inst);
+  c->b_fmt.assign(n_inst, 0);
   for (int32_t i = 0; i < n_inst; ++i) {
     const int32_t *f = &hfl[(size_t)8 * i];
     if (f[0] || f[1] || f[2]) {
       delete c;
       return fail(SI_ERR_INVALID, "init_batch: J[%d] must be finite, symmetric, zero diagonal", i);
     }
+    if (lowp) {
+      const bool fp8 = f[4] == 0 && prm->precision != SI_PREC_BF16X_HILOJ;
+      if (!fp8 && prm->precision == SI_PREC_BF16X_FP8J) {
+        delete c;
+        return fail(SI_ERR_UNSUPPORTED, "init_batch: J[%d] is not exact in FP8 e4m3", i);
+      }
+      c->b_fmt[i] = fp8 ? 1 : 2;
+    }
     c->b_n[i] = n[i];
-    c->b_npad[i] = (int32_t)round_up(n[i], BATCH_BM);
+    c->b_npad[i] = (int32_t)round_up(n[i], lowp ? BATCH_BF16_NPAD : BATCH_BM);
+    if (lowp) {
+      const int64_t nn = (int64_t)c->b_npad[i] * c->b_npad[i];
+      latot += c->b_fmt[i] == 1 ? nn : 2 * nn;  // bytes of the first J plane
+      if (c->b_fmt[i] == 2) lbtot += nn;        // BF16 elements of the lo plane
+    }
     c->b_jmax[i] = f[3] == 0 ? f[6] : -1;  // -1: not integer
     c->b_xoff[i] = xoff;
     xoff += (int64_t)r * n[i];
@@ -467,6 +493,13 @@ si_status spring_ising_init_batch(si_ctx **out, int32_t n_inst, const int32_t *n
   BINIT_HIP(c->alloc(&Jall, jtot));
   if (j8tot) BINIT_HIP(c->alloc(&J8all, j8tot));
   for (int b = 0; b < 4; ++b) BINIT_HIP(c->alloc(&sbuf[b], stot));
+  uint8_t *JAall = nullptr;
+  uint16_t *JBall = nullptr, *qball[2] = {nullptr, nullptr};
+  if (lowp) {
+    BINIT_HIP(c->alloc(&JAall, latot));
+    if (lbtot) BINIT_HIP(c->alloc(&JBall, lbtot));
+    for (int b = 0; b < 2; ++b) BINIT_HIP(c->alloc(&qball[b], stot));
+  }
   BINIT_HIP(c->alloc(&c->dt, prm->total_steps));
   BINIT_HIP(c->alloc(&c->zeta, prm->total_steps));
   BINIT_HIP(c->alloc(&c->S8, (int64_t)c->b_max_npad * c->r_pad));
@@ -481,6 +514,11 @@ si_status spring_ising_init_batch(si_ctx **out, int32_t n_inst, const int32_t *n
     c->b_p[b].resize(n_inst);
   }
   c->b_desc_host.resize(n_inst);
+  if (lowp) {
+    c->bb_desc_host.resize(n_inst);
+    for (int b = 0; b < 2; ++b) c->b_qb[b].resize(n_inst);
+  }
+  int64_t lao = 0, lbo = 0;
   for (int32_t i = 0; i < n_inst; ++i) {
     const int64_t nn = (int64_t)c->b_npad[i] * c->b_npad[i];
     c->b_J[i] = Jall + jo;
@@ -497,12 +535,38 @@ si_status spring_ising_init_batch(si_ctx **out, int32_t n_inst, const int32_t *n
     BINIT_HIP(launch_pack_state(nullptr, n[i], r, c->b_p[0][i], c->b_npad[i], c->r_pad, c->stream));
     c->b_desc_host[i] = BatchDesc{c->b_J[i], c->b_q[0][i], c->b_q[1][i], c->b_p[0][i], c->b_p[1][i],
                                   c->b_npad[i], 0};
+    if (lowp) {
+      const int64_t nr = (int64_t)c->r_pad * c->b_npad[i];
+      uint8_t *ja = JAall + lao;
+      uint16_t *jb = c->b_fmt[i] == 2 ? JBall + lbo : nullptr;
+      lao += c->b_fmt[i] == 1 ? nn : 2 * nn;
+      if (jb) lbo += nn;
+      c->b_qb[0][i] = qball[0] + (so - nr);
+      c->b_qb[1][i] = qball[1] + (so - nr);
+      BINIT_HIP(launch_pack_j_lowp(c->b_J[i], nn,
+                                   c->b_fmt[i] == 1 ? SI_PREC_BF16X_FP8J : SI_PREC_BF16X_HILOJ,
+                                   ja, jb, c->stream));
+      BINIT_HIP(launch_split_planes(c->b_q[0][i], c->b_qb[0][i], nr, 1, c->stream));
+      BBatchDesc d;
+      d.Ja = ja;
+      d.Jb = jb;
+      d.q[0] = c->b_q[0][i];
+      d.q[1] = c->b_q[1][i];
+      d.p[0] = c->b_p[0][i];
+      d.p[1] = c->b_p[1][i];
+      d.qb[0] = c->b_qb[0][i];
+      d.qb[1] = c->b_qb[1][i];
+      d.n_pad = c->b_npad[i];
+      d.fmt = c->b_fmt[i];
+      c->bb_desc_host[i] = d;
+    }
   }
   // work list, longest contraction first
   std::vector<int32_t> order(n_inst);
   for (int32_t i = 0; i < n_inst; ++i) order[i] = i;
   std::stable_sort(order.begin(), order.end(),
                    [&](int32_t x, int32_t y) { return c->b_npad[x] > c->b_npad[y]; });
+  // (the BF16 tiles are 64 x 64 like the FP32 ones)
   for (int32_t i : order)
     for (int32_t rt = 0; rt < c->b_npad[i] / BATCH_BM; ++rt)
       for (int32_t ct = 0; ct < c->r_pad / BATCH_BN; ++ct) c->b_items_host.push_back(int4{i, rt, ct, 0});
@@ -510,6 +574,11 @@ si_status spring_ising_init_batch(si_ctx **out, int32_t n_inst, const int32_t *n
   BINIT_HIP(c->alloc(&c->b_items, (int64_t)c->b_items_host.size()));
   BINIT_HIP(hipMemcpyAsync(c->b_desc, c->b_desc_host.data(), sizeof(BatchDesc) * n_inst,
                            hipMemcpyHostToDevice, c->stream));
+  if (lowp) {
+    BINIT_HIP(c->alloc(&c->bb_desc, n_inst));
+    BINIT_HIP(hipMemcpyAsync(c->bb_desc, c->bb_desc_host.data(), sizeof(BBatchDesc) * n_inst,
+                             hipMemcpyHostToDevice, c->stream));
+  }
   BINIT_HIP(hipMemcpyAsync(c->b_items, c->b_items_host.data(),
                            sizeof(int4) * c->b_items_host.size(), hipMemcpyHostToDevice, c->stream));
   build_schedules(*prm, c->host_dt, c->host_zeta);
@@ -622,6 +691,28 @@ static StepArgs step_args(si_ctx *c) {
 }
 
 static si_status do_steps_batch(si_ctx *c, int32_t n_steps) {
+  if (c->b_lowp) {
+    BStepArgs b;
+    memset(&b, 0, sizeof b);
+    b.dt = c->dt;
+    b.zeta = c->zeta;
+    b.h = nullptr;
+    b.r_pad = c->r_pad;
+    b.k = c->prm.k;
+    b.inv_m = 1.0f / c->prm.m;
+    b.qmax = c->prm.qmax;
+    b.pmax = c->prm.pmax;
+    b.order = c->prm.order;
+    b.wall = c->prm.wall;
+    for (int32_t s = 0; s < n_steps; ++s) {
+      b.t = c->t;
+      SI_HIP(c, launch_step_batch_bf16(b, c->bb_desc, c->b_items,
+                                       (int32_t)c->b_items_host.size(), c->cur, c->stream));
+      c->cur ^= 1;
+      c->t += 1;
+    }
+    return SI_OK;
+  }
   StepArgs a = step_args(c);
   for (int32_t s = 0; s < n_steps; ++s) {
     a.t = c->t;
@@ -995,6 +1086,9 @@ static si_status batch_set_state(si_ctx *c, const float *x, const float *p) {
                                 c->r_pad, c->stream));
     SI_HIP(c, launch_pack_state(p ? p + c->b_xoff[i] : nullptr, c->b_n[i], c->r,
                                 c->b_p[c->cur][i], c->b_npad[i], c->r_pad, c->stream));
+    if (c->b_lowp)
+      SI_HIP(c, launch_split_planes(c->b_q[c->cur][i], c->b_qb[c->cur][i],
+                                    (int64_t)c->r_pad * c->b_npad[i], 1, c->stream));
   }
   return SI_OK;
 }
@@ -1151,8 +1245,8 @@ si_status spring_ising_info(si_ctx *c, si_info *info) {
   info->resident_groups = c->poisoned ? 0 : resident_groups(c);
   info->resident_steps = info->resident_groups ? c->resident_min_steps : 0;
   if (c->n_inst)
-    snprintf(info->kernel_name, sizeof info->kernel_name, "step_batch_f32_%dx%d_x%d", BATCH_BM,
-             BATCH_BN, c->n_inst);
+    snprintf(info->kernel_name, sizeof info->kernel_name, "step_batch_%s_%dx%d_x%d",
+             c->b_lowp ? "bf16" : "f32", BATCH_BM, BATCH_BN, c->n_inst);
   else
     snprintf(info->kernel_name, sizeof info->kernel_name, "%s",
              shape_of(c->prm.precision, c->tile).name);

@@ -449,11 +449,12 @@ __global__ __launch_bounds__(C::NT) void step_bf16_kernel(BStepArgs a) {
     }
 }
 
+// One BM x BN output tile of one step on the direct-to-LDS pipeline: the
+// product over the BF16 planes, then the update of the FP32 master state and
+// the BF16 plane(s) of the new q.  Shared by the single-instance and the
+// batched kernels.
 template <class C, int ORDER, int WALL>
-__global__ __launch_bounds__(C::NT) void step_bf16_dma_kernel(BStepArgs a) {
-  __shared__ __attribute__((aligned(16))) uint8_t smem[C::LDS_BYTES];
-  const int t = xcd_tile(blockIdx.x, gridDim.x), ncol = a.r_pad / C::BN;
-  const int m0 = (t / ncol) * C::BM, n0 = (t % ncol) * C::BN;
+__device__ __forceinline__ void bf16_dma_tile(const BStepArgs &a, int m0, int n0, uint8_t *smem) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wy = wave / C::WN, wx = wave % C::WN;
   // State of this lane's outputs.  It is loaded before the contraction, so
@@ -523,6 +524,66 @@ __global__ __launch_bounds__(C::NT) void step_bf16_dma_kernel(BStepArgs a) {
         }
       }
     }
+}
+
+template <class C, int ORDER, int WALL>
+__global__ __launch_bounds__(C::NT) void step_bf16_dma_kernel(BStepArgs a) {
+  __shared__ __attribute__((aligned(16))) uint8_t smem[C::LDS_BYTES];
+  const int t = xcd_tile(blockIdx.x, gridDim.x), ncol = a.r_pad / C::BN;
+  bf16_dma_tile<C, ORDER, WALL>(a, (t / ncol) * C::BM, (t % ncol) * C::BN, smem);
+}
+
+// Batched precision form: one launch advances every instance by one step.
+// Work item (instance, row tile, column tile) as in the FP32 batch; each
+// instance carries its own J format: FP8 e4m3 (J exact in FP8) on the
+// 64x64 tile with 128-deep slabs, hi + lo BF16 otherwise on the 64x64 tile
+// with 64-deep slabs -- the same tile bodies as the single-instance tiles
+// of those shapes, so every instance matches its standalone run bit for bit.
+using BatchFp8Cfg = Bf16DmaCfg<BATCH_BM, BATCH_BN, 2, 2, 128, 1, 1, 3>;
+using BatchHiloCfg = Bf16DmaCfg<BATCH_BM, BATCH_BN, 2, 2, 64, 2, 1, 3>;
+static_assert(BatchFp8Cfg::NT == BatchHiloCfg::NT, "one block shape for both formats");
+constexpr int BATCH_BF16_LDS = BatchFp8Cfg::LDS_BYTES > BatchHiloCfg::LDS_BYTES
+                                   ? BatchFp8Cfg::LDS_BYTES
+                                   : BatchHiloCfg::LDS_BYTES;
+
+template <int ORDER, int WALL>
+__global__ __launch_bounds__(BatchFp8Cfg::NT) void step_batch_bf16_kernel(
+    BStepArgs base, const BBatchDesc *__restrict__ descs, const int4 *__restrict__ items, int cur) {
+  __shared__ __attribute__((aligned(16))) uint8_t smem[BATCH_BF16_LDS];
+  const int4 it = items[blockIdx.x];
+  const BBatchDesc d = descs[it.x];
+  BStepArgs a = base;
+  a.Ja = d.Ja;
+  a.Jb = d.Jb;
+  a.q_in = d.q[cur];
+  a.p_in = d.p[cur];
+  a.q_out = d.q[cur ^ 1];
+  a.p_out = d.p[cur ^ 1];
+  a.qb_in = d.qb[cur];
+  a.qb_out = d.qb[cur ^ 1];
+  a.ld = d.n_pad;
+  a.n_pad = d.n_pad;
+  a.plane_stride = (int64_t)d.n_pad * base.r_pad;
+  a.h = nullptr;
+  if (d.fmt == 1)
+    bf16_dma_tile<BatchFp8Cfg, ORDER, WALL>(a, it.y * BATCH_BM, it.z * BATCH_BN, smem);
+  else
+    bf16_dma_tile<BatchHiloCfg, ORDER, WALL>(a, it.y * BATCH_BM, it.z * BATCH_BN, smem);
+}
+
+hipError_t launch_step_batch_bf16(const BStepArgs &base, const BBatchDesc *descs,
+                                  const int4 *items, int32_t n_items, int32_t cur,
+                                  hipStream_t s) {
+  if (n_items <= 0) return hipSuccess;
+  dim3 grid(n_items), block(BatchFp8Cfg::NT);
+  switch (base.order * 2 + base.wall) {
+    case 0: step_batch_bf16_kernel<SI_ORDER_PAPER, SI_WALL_CLAMP><<<grid, block, 0, s>>>(base, descs, items, cur); break;
+    case 1: step_batch_bf16_kernel<SI_ORDER_PAPER, SI_WALL_INELASTIC><<<grid, block, 0, s>>>(base, descs, items, cur); break;
+    case 2: step_batch_bf16_kernel<SI_ORDER_SYMPLECTIC, SI_WALL_CLAMP><<<grid, block, 0, s>>>(base, descs, items, cur); break;
+    case 3: step_batch_bf16_kernel<SI_ORDER_SYMPLECTIC, SI_WALL_INELASTIC><<<grid, block, 0, s>>>(base, descs, items, cur); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 template <class C>

@@ -30,7 +30,9 @@ SI_PREC_BF16X_FP8J = 1
 SI_PREC_BF16X_BF16J = 2
 SI_PREC_BF16X_HILOJ = 3
 SI_PREC_BF16X3_EXACTJ = 4
-PRECISIONS = {"fp32": 0, "bf16x_fp8j": 1, "bf16x_bf16j": 2, "bf16x_hiloj": 3, "bf16x3_exactj": 4}
+SI_PREC_BF16X_MIXEDJ = 5
+PRECISIONS = {"fp32": 0, "bf16x_fp8j": 1, "bf16x_bf16j": 2, "bf16x_hiloj": 3, "bf16x3_exactj": 4,
+              "bf16x_mixedj": 5}
 
 
 class si_params(ctypes.Structure):
@@ -306,6 +308,8 @@ class SpringIsingBatch:
         self.r = int(x0s[0].shape[0])
         prm = spring_ising_default_params(total_steps)
         for key, val in overrides.items():
+            if key == "precision" and isinstance(val, str):
+                val = PRECISIONS[val]
             setattr(prm, key, val)
         self.total_steps = int(prm.total_steps)
         self.device = Js[0].device

@@ -14,11 +14,11 @@ R = 64
 BATCH_TILE = 14  # the single-instance tile with the batched kernel's configuration
 
 
-def _batch(specs, S, r=R):
+def _batch(specs, S, r=R, **kw):
     si = ensure_built()
     Js = [instances.make_J(n, kind, 10 + i) for i, (n, kind) in enumerate(specs)]
     xs = [instances.make_x0(n, r, 20 + i) for i, (n, kind) in enumerate(specs)]
-    b = si.SpringIsingBatch([to_dev(J) for J in Js], [to_dev(x) for x in xs], total_steps=S)
+    b = si.SpringIsingBatch([to_dev(J) for J in Js], [to_dev(x) for x in xs], total_steps=S, **kw)
     return b, Js, xs
 
 
@@ -125,3 +125,120 @@ def test_batch_full_workload_generated_on_device():
     info = b.info()
     announce(f"  {info['kernel_name']}: {el * 1e3:.3f} ms/step, total spins {info['n']}")
     b.close()
+
+
+# ---------------------------------------------------------------------------
+# Batched precision form: FP8 J for the +-1 instances, hi + lo BF16 J for
+# the Gaussian ones, in one grouped launch per step.
+# ---------------------------------------------------------------------------
+FORM_TILE = {"pm1": ("bf16x_fp8j", 9), "gauss": ("bf16x_hiloj", 7)}
+
+
+def test_bf16_batch_equals_standalone_runs():
+    import torch
+    si = ensure_built()
+    announce("BF16 batch (FP8 / hi+lo per instance) vs standalone runs, bit for bit")
+    S = 300
+    b, Js, xs = _batch(SIZES, S, precision="bf16x_mixedj")
+    assert b.info()["kernel_name"].startswith("step_batch_bf16")
+    b.run(150)
+    xb, pb, t = b.state()
+    eb = b.energy(exact=False)
+    torch.cuda.synchronize()
+    assert t == 150
+    for i, (n, kind) in enumerate(SIZES):
+        form, tile = FORM_TILE[kind]
+        m = si.SpringIsing(to_dev(Js[i]), to_dev(xs[i]), total_steps=S, precision=form, tile=tile)
+        m.run(150)
+        x, p, _ = m.state()
+        e = m.energy(exact=False)
+        torch.cuda.synchronize()
+        assert np.array_equal(x.cpu().numpy(), xb[i].cpu().numpy()), (i, n, kind)
+        assert np.array_equal(p.cpu().numpy(), pb[i].cpu().numpy()), (i, n, kind)
+        assert np.array_equal(e.cpu().numpy(), eb[i].cpu().numpy()), (i, n, kind)
+        m.close()
+    b.close()
+
+
+def test_bf16_batch_one_step_bound():
+    # One step from a random state: every instance within the element-wise
+    # bound that BF16 positions (and the hi + lo residual of J) allow.
+    import torch
+    announce("BF16 batch one-step bound vs FP64 oracle")
+    S = 100
+    specs = SIZES[:4]
+    b, Js, _ = _batch(specs, S, precision="bf16x_mixedj")
+    xs = [instances.random_state(n, R, 60 + i, scale=1.4) for i, (n, _) in enumerate(specs)]
+    ps = [instances.random_state(n, R, 70 + i, scale=1.9) for i, (n, _) in enumerate(specs)]
+    b.set_state([to_dev(x) for x in xs], [to_dev(p) for p in ps], 37)
+    b.step()
+    xb, pb, _ = b.state()
+    torch.cuda.synchronize()
+    dt, zeta = oracle_schedules(S)
+    d, z = float(dt[37]), float(zeta[37])
+    for i, (n, kind) in enumerate(specs):
+        J64 = Js[i].astype(np.float64)
+        Q, P = oracle.step(J64, xs[i].T.astype(np.float64), ps[i].T.astype(np.float64), d, z,
+                           qmax=QMAX)
+        mag = np.abs(J64) @ np.abs(xs[i].T.astype(np.float64))
+        jrel = 2.0 ** -16 if kind == "gauss" else 0.0
+        bound = d * z * mag * (2.0 ** -8 + jrel) * 1.01 + 4 * 2.0 ** -24 * (np.abs(P) + 2.0) \
+            + d * z * mag * n * 2.0 ** -24
+        err = np.abs(pb[i].cpu().numpy().T - P)
+        assert np.all(err <= bound), (i, err.max())
+        assert np.abs(xb[i].cpu().numpy().T - Q).max() <= 4e-7
+        announce(f"  instance {i} N={n} {kind}: max one-step momentum error {err.max():.2e}")
+    b.close()
+
+
+def test_bf16_batch_format_rules():
+    si = ensure_built()
+    with pytest.raises(si.SpringIsingError) as err:   # Gaussian J is not exact in FP8
+        _batch(SIZES[:2], 10, precision="bf16x_fp8j")
+    assert err.value.status == si.SI_ERR_UNSUPPORTED
+    with pytest.raises(si.SpringIsingError) as err:   # no batched form
+        _batch(SIZES[:2], 10, precision="bf16x3_exactj")
+    assert err.value.status == si.SI_ERR_UNSUPPORTED
+    b, _, _ = _batch(SIZES[:2], 10, precision="bf16x_hiloj")  # hi + lo for every instance
+    b.run(10)
+    b.close()
+
+
+def test_bf16_batch_full_workload_vs_fp32():
+    # The 256-instance workload in both forms for 3000 steps: per-instance
+    # final energies agree in distribution (z-scores of the mean difference
+    # over 64 replicas behave like a standard normal sample), and the BF16
+    # batch is faster per step.
+    import time
+
+    import torch
+    si = ensure_built()
+    announce("256-instance batch, FP32 vs BF16 (FP8 / hi+lo), 3000 steps")
+    S = 3000
+    recipe = instances.make_batch(256, 0)
+    dev = torch.device("cuda:0")
+    Js = [instances.make_J_torch(n, kind, seed, dev) for n, kind, seed in recipe]
+    xs = [instances.make_x0_torch(n, R, seed, device=dev) for n, kind, seed in recipe]
+    torch.cuda.synchronize()
+    res = {}
+    for form in ("fp32", "bf16x_mixedj"):
+        b = si.SpringIsingBatch(Js, xs, total_steps=S, precision=form)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b.run(S)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        e = [v.cpu().numpy().astype(np.float64) for v in b.energy(exact=False)]
+        res[form] = (e, el / S)
+        announce(f"  {form} ({b.info()['kernel_name']}): {1e3 * el / S:.3f} ms/step")
+        b.close()
+    del Js, xs
+    z = []
+    for e32, elp in zip(res["fp32"][0], res["bf16x_mixedj"][0]):
+        se = np.sqrt(e32.var() / R + elp.var() / R)
+        z.append((elp.mean() - e32.mean()) / se if se > 0 else 0.0)
+    z = np.array(z)
+    announce(f"  per-instance z of mean final energy: mean {z.mean():+.3f}, sd {z.std():.3f}, "
+             f"max |z| {np.abs(z).max():.2f}")
+    assert abs(z.mean()) < 0.35 and z.std() < 1.4 and (np.abs(z) > 4).mean() < 0.02
+    assert res["bf16x_mixedj"][1] < res["fp32"][1]
