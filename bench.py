@@ -17,6 +17,9 @@ FP32 final energies; each form runs the same schedule with the exact energy
 of every replica checked every 50 steps (check cost included, timed with
 HIP events on the stream the kernels run on) and its time-to-target is the
 event time of the first check with a replica at or below the target.
+The batched configuration (256 uneven instances, R = 64) is timed per step
+in FP32 and in the BF16 form, and against the same instances stepped one
+after another.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
 """
@@ -82,6 +85,48 @@ def cpu_baseline(budget_s: float = 15.0):
                       f"{el:.1f} s), extrapolated per iteration"}
 
 
+def batched_form(si, steps=300, n_inst=256, r=64):
+    """The batched configuration (256 uneven instances, N in [64, 4096], half
+    +-1 and half Gaussian, R = 64): ms per step of all instances together,
+    batched in FP32 and in the BF16 form (FP8 / hi + lo J), and the same
+    instances stepped one after another as single FP32 contexts."""
+    import torch
+
+    from paper_2305_07187_amd import instances
+    dev = torch.device("cuda:0")
+    recipe = instances.make_batch(n_inst, 0)
+    Js = [instances.make_J_torch(n, kind, seed, dev) for n, kind, seed in recipe]
+    xs = [instances.make_x0_torch(n, r, seed, device=dev) for n, kind, seed in recipe]
+    torch.cuda.synchronize()
+    out = {"workload": f"{n_inst} instances, N uniform in [64, 4096] (sum {sum(n for n, _, _ in recipe)}), "
+                       f"half +-1 half Gaussian, R={r}", "steps_timed": steps}
+    for form in ("fp32", "bf16x_mixedj"):
+        b = si.SpringIsingBatch(Js, xs, total_steps=steps + 10, precision=form)
+        b.run(10)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b.run(steps)
+        torch.cuda.synchronize()
+        out[f"{form}_batched_ms_per_step"] = 1000.0 * (time.perf_counter() - t0) / steps
+        out[f"{form}_kernel"] = b.info()["kernel_name"]
+        b.close()
+    seq = 0.0
+    for J, x in zip(Js, xs):
+        m = si.SpringIsing(J, x, total_steps=30)
+        m.run(5)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        m.run(25)
+        torch.cuda.synchronize()
+        seq += (time.perf_counter() - t0) / 25
+        m.close()
+    out["fp32_sequential_ms_per_step"] = 1000.0 * seq
+    out["batched_vs_sequential_fp32"] = seq * 1000.0 / out["fp32_batched_ms_per_step"]
+    out["bf16_vs_fp32_batched"] = (out["fp32_batched_ms_per_step"] /
+                                   out["bf16x_mixedj_batched_ms_per_step"])
+    return out
+
+
 def timed_runs(model, x0, iters, steps, warmup, stream):
     exact = bool(model.info()["j_integer"])
     """Full runs (reset, iters steps, energy); per-run HIP events bracket the
@@ -138,6 +183,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the precision-form lines")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched-form timing")
     ap.add_argument("--iters", type=int, default=ITERS, help=argparse.SUPPRESS)
     # other shapes, for profiling the precision configurations (not bench lines)
     ap.add_argument("--n", type=int, default=N, help=argparse.SUPPRESS)
@@ -253,9 +299,11 @@ def main():
             forms[name]["ttt_speedup_vs_fp32"] = (t32 / tf) if (t32 and tf) else None
         out["time_to_target"] = {"target_energy": target, "check_every": CHECK_EVERY,
                                  "forms": forms}
+    model.close()
+    if fp32_line and not args.no_batched and (n, r, args.couplings) == (N, R, "pm1"):
+        out["batched_form"] = batched_form(si)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
-    model.close()
     print(json.dumps(out))
 
 
