@@ -31,18 +31,18 @@ def _torch_replay(J, Q0, dt, zeta, k=0.5, m=1.0, qmax=F32_SQRT2, pmax=2.0):
     return loss.item(), d.grad.numpy(), z.grad.numpy()
 
 
-@pytest.mark.parametrize("n,r,S", [(10, 3, 40), (24, 5, 120)])
-def test_adjoint_matches_autograd_replay(n, r, S):
+@pytest.mark.parametrize("n,r,S,m", [(10, 3, 40, 1.0), (24, 5, 120, 1.0), (16, 4, 80, 2.0)])
+def test_adjoint_matches_autograd_replay(n, r, S, m):
     J = instances.make_pm1(n, 5).astype(np.float64)
     Q0 = instances.make_x0(n, r, 2).T.astype(np.float64)
     dt = oracle.dt_schedule(S).astype(np.float64)
     zeta = oracle.zeta_schedule(S).astype(np.float64)
-    L, gd, gz = oracle.relaxed_energy_grad(J, Q0, None, dt, zeta, qmax=F32_SQRT2)
-    Lt, gdt, gzt = _torch_replay(J, Q0, dt, zeta)
+    L, gd, gz = oracle.relaxed_energy_grad(J, Q0, None, dt, zeta, m=m, qmax=F32_SQRT2)
+    Lt, gdt, gzt = _torch_replay(J, Q0, dt, zeta, m=m)
     assert L == pytest.approx(Lt, rel=1e-12)
     np.testing.assert_allclose(gd, gdt, rtol=1e-9, atol=1e-9 * np.abs(gdt).max())
     np.testing.assert_allclose(gz, gzt, rtol=1e-9, atol=1e-9 * np.abs(gzt).max())
-    assert L == pytest.approx(oracle.relaxed_energy(J, oracle.run(J, Q0, None, dt, zeta,
+    assert L == pytest.approx(oracle.relaxed_energy(J, oracle.run(J, Q0, None, dt, zeta, m=m,
                                                                    qmax=F32_SQRT2)["Q"]), rel=1e-12)
 
 

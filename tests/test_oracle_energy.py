@@ -87,6 +87,36 @@ def test_bruteforce_enumerates_every_state_once():
     np.testing.assert_array_equal(energies, energies[comp])
 
 
+def test_bruteforce_index_convention():
+    # State index x has spin i down exactly when bit i of x is set: the
+    # table entry 2^i is the state with only spin i flipped.
+    n = 7
+    J = instances.make_gauss(n, 13).astype(np.float64)
+    _, _, energies = oracle.ground_state_bruteforce(J)
+    for i in range(n):
+        s = np.ones(n, dtype=np.int64)
+        s[i] = -1
+        np.testing.assert_array_equal(all_states(n, 1 << i, (1 << i) + 1)[0], s)
+        assert abs(energies[1 << i] - oracle.ising_energy_pairs(J.tolist(), s.tolist())) < 1e-12
+    x = 0b1010011
+    s = np.array([-1 if (x >> i) & 1 else 1 for i in range(n)])
+    assert abs(energies[x] - oracle.ising_energy_pairs(J.tolist(), s.tolist())) < 1e-12
+
+
+@pytest.mark.parametrize("kind", ["pm1", "gauss"])
+def test_diagonal_never_enters_energy(kind):
+    # Eq. (1) sums over pairs i < j only, so J_ii cannot change H.
+    n = 12
+    J = instances.make_J(n, kind, 21).astype(np.float64)
+    D = J + np.diag(np.arange(1, n + 1, dtype=np.float64) * (3 if kind == "pm1" else 0.37))
+    S = _rand_spins(n, 6, 9)
+    e0 = oracle.ising_energy(J, S)
+    e1 = oracle.ising_energy(D, S)
+    np.testing.assert_allclose(e1, e0, rtol=0, atol=1e-12)
+    for r in range(3):
+        assert abs(oracle.ising_energy_pairs(D.tolist(), S[:, r].tolist()) - e0[r]) < 1e-12
+
+
 def test_single_flip_local_field():
     # Flipping spin t changes E by 2 s_t (sum_j J_tj s_j + h_t).
     n = 25
