@@ -109,6 +109,48 @@ def test_adjoint_full_size_first_steps():
     assert _rel(gd, gdo) <= 1e-3 and _rel(gz, gzo) <= 1e-3
 
 
+def test_adjoint_vs_device_finite_differences():
+    # At the differentiation workload's shape (N=2000, R=64), in the smooth
+    # regime (zeta * lambda_max < k, walls never reached): the adjoint's
+    # directional derivatives against central differences of the device's
+    # own forward map, with the loss evaluated in FP64 from the final
+    # positions.  The perturbations are the exact FP32 schedule changes.
+    import torch
+    si = ensure_built()
+    n, r, S = 2000, 64, 100
+    announce(f"adjoint vs device central differences N={n} R={r} S={S}")
+    J = instances.make_pm1(n, 0)
+    J64 = J.astype(np.float64)
+    x0 = instances.make_x0(n, r, 0)
+    dt = np.full(S, 0.1, np.float32)
+    zeta = np.linspace(0.002, 0.005, S).astype(np.float32)
+    L, gd, gz = _grad(J, x0, dt, zeta, ckpt=25)
+    m = si.SpringIsing(to_dev(J), to_dev(x0), total_steps=S)
+
+    def loss(d, z):
+        m.set_state(to_dev(x0), None, 0)
+        m.set_schedule(to_dev(d), to_dev(z))
+        m.run(S)
+        x, p, _ = m.state()
+        torch.cuda.synchronize()
+        q = x.cpu().numpy().T.astype(np.float64)
+        assert np.abs(q).max() < QMAX and np.abs(p.cpu().numpy()).max() < 2.0
+        return oracle.relaxed_energy(J64, q)
+
+    assert loss(dt, zeta) == pytest.approx(L, rel=1e-6)
+    rng = np.random.default_rng(5)
+    h = 1e-2
+    for _ in range(3):
+        u, v = rng.standard_normal(S), rng.standard_normal(S)
+        dp, dm = (dt * (1 + h * u)).astype(np.float32), (dt * (1 - h * u)).astype(np.float32)
+        zp, zm = (zeta * (1 + h * v)).astype(np.float32), (zeta * (1 - h * v)).astype(np.float32)
+        diff = loss(dp, zp) - loss(dm, zm)
+        want = gd @ (dp.astype(np.float64) - dm) + gz @ (zp.astype(np.float64) - zm)
+        announce(f"  central difference {diff:.6e} vs adjoint {want:.6e}")
+        assert abs(diff - want) <= 2e-3 * abs(want) + 1e-6 * abs(L)
+    m.close()
+
+
 def test_adjoint_full_workload_runs():
     # the full differentiation workload: N=2000, R=64, 2000 steps, checkpoints
     # every 100; deterministic and invariant to the checkpoint interval
