@@ -139,14 +139,19 @@ __device__ __forceinline__ void f32_mainloop_dma(const float *__restrict__ A,
   for (int s = 0; s < S - 1; ++s)
     if (s < nk) issue(s, s);
   const int ra = wy * C::WTM + lrow, rb = wx * C::WTN + lrow;  // fragment rows (i = j = 0)
+  // ring slots read and written this iteration (kt % S and (kt + S - 1) % S,
+  // kept as counters so that no division runs in the loop)
+  int rd = 0, wr = S - 1;
   for (int kt = 0; kt < nk; ++kt) {
     if (kt + S - 1 < nk) {
       wait_vm_barrier<(S - 2) * L>();
-      issue(kt + S - 1, (kt + S - 1) % S);
+      issue(kt + S - 1, wr);
     } else {
       wait_vm_barrier<0>();
     }
-    const float *st = smem + (kt % S) * SLAB;
+    wr = wr + 1 == S ? 0 : wr + 1;
+    const float *st = smem + rd * SLAB;
+    rd = rd + 1 == S ? 0 : rd + 1;
     // fragments of the next contraction step are read while the MFMAs of
     // the current one run
     floatx4 a[2][C::TM], b[2][C::TN];

@@ -45,6 +45,7 @@ struct StepArgs {
   const float *h;     // field [n_pad] or nullptr
   int32_t t;          // schedule index of this step
   int32_t ld;         // n_pad
+  int32_t n;          // spins; the contraction stops at n rounded up to the slab depth
   int32_t n_pad, r_pad;
   float k, inv_m, qmax, pmax;
   int32_t order;      // si_order
@@ -78,7 +79,7 @@ constexpr int BATCH_BM = 64, BATCH_BN = 64;
 struct BatchDesc {
   const float *J;         // [n_pad][n_pad]
   float *q0, *q1, *p0, *p1;  // [r_pad][n_pad] ping-pong state
-  int32_t n_pad, pad_;
+  int32_t n_pad, n;
 };
 hipError_t launch_step_batch_f32(const StepArgs &a, const BatchDesc *descs, const int4 *items,
                                  int32_t n_items, int32_t cur, hipStream_t s);

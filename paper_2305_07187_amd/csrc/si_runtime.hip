@@ -534,7 +534,7 @@ si_status spring_ising_init_batch(si_ctx **out, int32_t n_inst, const int32_t *n
     BINIT_HIP(launch_pack_state(x0[i], n[i], r, c->b_q[0][i], c->b_npad[i], c->r_pad, c->stream));
     BINIT_HIP(launch_pack_state(nullptr, n[i], r, c->b_p[0][i], c->b_npad[i], c->r_pad, c->stream));
     c->b_desc_host[i] = BatchDesc{c->b_J[i], c->b_q[0][i], c->b_q[1][i], c->b_p[0][i], c->b_p[1][i],
-                                  c->b_npad[i], 0};
+                                  c->b_npad[i], n[i]};
     if (lowp) {
       const int64_t nr = (int64_t)c->r_pad * c->b_npad[i];
       uint8_t *ja = JAall + lao;
@@ -678,6 +678,7 @@ static StepArgs step_args(si_ctx *c) {
   a.zeta = c->zeta;
   a.h = c->has_field ? c->hf : nullptr;
   a.ld = c->n_pad;
+  a.n = c->n;
   a.n_pad = c->n_pad;
   a.r_pad = c->r_pad;
   a.k = c->prm.k;
@@ -733,6 +734,7 @@ static si_status do_steps(si_ctx *c, int32_t n_steps) {
   a.zeta = c->zeta;
   a.h = c->has_field ? c->hf : nullptr;
   a.ld = c->n_pad;
+  a.n = c->n;
   a.n_pad = c->n_pad;
   a.r_pad = c->r_pad;
   a.k = c->prm.k;

@@ -320,14 +320,18 @@ __device__ __forceinline__ void bf16_mainloop_dma(const BStepArgs &a, int m0, in
 #pragma unroll
   for (int s = 0; s < S - 1; ++s)
     if (s < nk) issue(s, s);
+  // ring slots read and written this iteration, kept as counters
+  int rd = 0, wr = S - 1;
   for (int kt = 0; kt < nk; ++kt) {
     if (kt + S - 1 < nk) {
       wait_vm_barrier_b<(S - 2) * C::L>();
-      issue(kt + S - 1, (kt + S - 1) % S);
+      issue(kt + S - 1, wr);
     } else {
       wait_vm_barrier_b<0>();
     }
-    const uint8_t *st = smem + (kt % S) * C::SLOT;
+    wr = wr + 1 == S ? 0 : wr + 1;
+    const uint8_t *st = smem + rd * C::SLOT;
+    rd = rd + 1 == S ? 0 : rd + 1;
 #pragma unroll
     for (int kk = 0; kk < C::BK; kk += 32) {
       bf16x8 fa[C::JP][C::TM][2], fb[C::QP][C::TN][2];

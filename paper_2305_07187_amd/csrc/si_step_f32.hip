@@ -44,6 +44,14 @@ __device__ __forceinline__ void update(float q, float p, float f, float dt, floa
   if (WALL == SI_WALL_INELASTIC && fabsf(u) > qmax) pn = 0.f;
 }
 
+// Contraction length for n spins: n rounded up to the slab depth.  Columns
+// of J beyond n are zero padding, so stopping there drops only exact zeros.
+template <class C>
+__device__ __forceinline__ int kdim(int n, int ld) {
+  const int k = (n + C::BK - 1) / C::BK * C::BK;
+  return k < ld ? k : ld;
+}
+
 // One BM x BN output tile of one step: contraction over k in [0, K) of the
 // rows m0.. of J (leading dimension ld) with the replicas n0.. of q_in, then
 // the update.  Shared by the single-instance and the batched kernels.
@@ -51,7 +59,7 @@ template <class C, int ORDER, int WALL>
 __device__ __forceinline__ void step_tile(const StepArgs &a, const float *__restrict__ Jm,
                                           const float *__restrict__ q_in,
                                           const float *__restrict__ p_in, float *__restrict__ q_out,
-                                          float *__restrict__ p_out, int ld, int m0, int n0,
+                                          float *__restrict__ p_out, int ld, int K, int m0, int n0,
                                           float *smem) {
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
@@ -78,9 +86,9 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, const float *__rest
 
   typename C::acc_t acc[C::TM][C::TN];
   if constexpr (C::STAGES > 0)
-    f32_mainloop_dma<C>(Jm, q_in, ld, ld, m0, n0, acc, smem);
+    f32_mainloop_dma<C>(Jm, q_in, ld, K, m0, n0, acc, smem);
   else
-    f32_mainloop<C, B_PLAIN>(Jm, q_in, ld, ld, m0, n0, acc, smem);
+    f32_mainloop<C, B_PLAIN>(Jm, q_in, ld, K, m0, n0, acc, smem);
 
   const float dt = a.dt[a.t], zeta = a.zeta[a.t];
 #pragma unroll
@@ -123,8 +131,8 @@ template <class C, int ORDER, int WALL>
 __global__ __launch_bounds__(C::NT) void step_f32_kernel(StepArgs a) {
   __shared__ __attribute__((aligned(16))) float smem[C::LDS_FLOATS];
   const int t = xcd_tile(blockIdx.x, gridDim.x), ncol = a.r_pad / C::BN;
-  step_tile<C, ORDER, WALL>(a, a.J, a.q_in, a.p_in, a.q_out, a.p_out, a.ld, (t / ncol) * C::BM,
-                            (t % ncol) * C::BN, smem);
+  step_tile<C, ORDER, WALL>(a, a.J, a.q_in, a.p_in, a.q_out, a.p_out, a.ld, kdim<C>(a.n, a.ld),
+                            (t / ncol) * C::BM, (t % ncol) * C::BN, smem);
 }
 
 // Grid-wide barrier of a resident launch, without atomic read-modify-write:
@@ -181,7 +189,7 @@ __global__ __launch_bounds__(C::NT) void resident_f32_kernel(StepArgs a, Residen
   const int wave = threadIdx.x >> 6;
   const int wy = wave / C::WN, wx = wave % C::WN;
   constexpr int G = C::M::NACC / 4;
-  const int ld = a.ld;
+  const int ld = a.ld, K = kdim<C>(a.n, a.ld);
   floatx4 q4[C::TM][G][C::TN], p4[C::TM][G][C::TN], h4[C::TM][G];
   int cur = r.cur;
 #pragma unroll
@@ -201,9 +209,9 @@ __global__ __launch_bounds__(C::NT) void resident_f32_kernel(StepArgs a, Residen
   for (int s = 0; s < r.n_steps; ++s) {
     typename C::acc_t acc[C::TM][C::TN];
     if constexpr (C::STAGES > 0)
-      f32_mainloop_dma<C>(a.J, r.q[cur], ld, ld, m0, n0, acc, smem);
+      f32_mainloop_dma<C>(a.J, r.q[cur], ld, K, m0, n0, acc, smem);
     else
-      f32_mainloop<C, B_PLAIN>(a.J, r.q[cur], ld, ld, m0, n0, acc, smem);
+      f32_mainloop<C, B_PLAIN>(a.J, r.q[cur], ld, K, m0, n0, acc, smem);
     const float dt = a.dt[a.t + s], zeta = a.zeta[a.t + s];
     float *qd = r.q[cur ^ 1];
 #pragma unroll
@@ -253,7 +261,8 @@ __global__ __launch_bounds__(C::NT) void step_batch_f32_kernel(StepArgs a,
   const int4 it = items[blockIdx.x];
   const BatchDesc d = descs[it.x];
   step_tile<C, ORDER, WALL>(a, d.J, cur ? d.q1 : d.q0, cur ? d.p1 : d.p0, cur ? d.q0 : d.q1,
-                            cur ? d.p0 : d.p1, d.n_pad, it.y * C::BM, it.z * C::BN, smem);
+                            cur ? d.p0 : d.p1, d.n_pad, kdim<C>(d.n, d.n_pad), it.y * C::BM,
+                            it.z * C::BN, smem);
 }
 
 // Tile table: id, BM, BN, waves (WM x WN), MFMA block edge, slab depth BK,
