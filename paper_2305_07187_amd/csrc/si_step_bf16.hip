@@ -20,6 +20,7 @@
 // Each lane fills its 8 slots with 8 contiguous contraction indices read by
 // one 128-bit LDS load, identically for A and B, so the product sums every
 // index exactly once.
+#include "si_epilogue.h"
 #include "si_internal.h"
 
 namespace si {
@@ -385,72 +386,72 @@ __device__ __forceinline__ void bf16_mainloop_dma(const BStepArgs &a, int m0, in
   wait_vm_barrier_b<0>();
 }
 
-template <int ORDER, int WALL>
-__device__ __forceinline__ void update_b(float q, float p, float f, float dt, float zeta, float k,
-                                         float inv_m, float qmax, float pmax, float &qn,
-                                         float &pn) {
-  const float c = dt * inv_m;
-  const float force = fmaf(zeta, f, -k * q);
-  const float v = fmaf(dt, force, p);
-  pn = fminf(fmaxf(v, -pmax), pmax);
-  const float u = ORDER == SI_ORDER_PAPER ? fmaf(c, p, q) : fmaf(c, pn, q);
-  qn = fminf(fmaxf(u, -qmax), qmax);
-  if (WALL == SI_WALL_INELASTIC && fabsf(u) > qmax) pn = 0.f;
+
+// Update of one BF16-form tile: F through LDS into the state's layout,
+// then the FP32 master state and the BF16 plane(s) of the new q.
+template <class T, int QP, int ORDER, int WALL>
+__device__ __forceinline__ void bf16_update(const BStepArgs &a, int m0, int n0, float *t,
+                                            const floatx4 (&q4)[T::CPT],
+                                            const floatx4 (&p4)[T::CPT]) {
+  EpiArgs e;
+  e.q_in = a.q_in;
+  e.p_in = a.p_in;
+  e.h = a.h;
+  e.q_out = a.q_out;
+  e.p_out = a.p_out;
+  e.qb_out = a.qb_out;
+  e.plane_stride = a.plane_stride;
+  e.mask_out = nullptr;
+  e.ld = a.ld;
+  e.m0 = m0;
+  e.n0 = n0;
+  e.dt = a.dt[a.t];
+  e.zeta = a.zeta[a.t];
+  e.k = a.k;
+  e.inv_m = a.inv_m;
+  e.qmax = a.qmax;
+  e.pmax = a.pmax;
+  epi_apply<T, ORDER, WALL, QP>(t, e, q4, p4);
+}
+
+// The 32x32 accumulator blocks of this wave into the LDS tile (32x32x16
+// layout: lane l holds rows 8(v/4) + 4(l/32) + v%4 of column l%32).
+template <class C>
+__device__ __forceinline__ void bf16_put(float *t, int ld, const floatx16 (&acc)[C::TM][C::TN]) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wy = wave / C::WN, wx = wave % C::WN;
+#pragma unroll
+  for (int i = 0; i < C::TM; ++i)
+#pragma unroll
+    for (int g = 0; g < 4; ++g)
+#pragma unroll
+      for (int j = 0; j < C::TN; ++j)
+        epi_put(t, ld, wy * C::WTM + i * 32 + g * 8 + (lane / 32) * 4,
+                wx * C::WTN + j * 32 + (lane % 32), acc[i][j][4 * g], acc[i][j][4 * g + 1],
+                acc[i][j][4 * g + 2], acc[i][j][4 * g + 3]);
 }
 
 template <class C, int ORDER, int WALL>
 __global__ __launch_bounds__(C::NT) void step_bf16_kernel(BStepArgs a) {
   __shared__ __attribute__((aligned(16))) uint16_t smem[C::LDS_ELEMS];
+  using T = EpiTile<C::BM, C::BN, C::NT>;
+  static_assert(T::BYTES <= C::LDS_ELEMS * 2, "the update tile fits in the main loop's LDS");
   const int t = xcd_tile(blockIdx.x, gridDim.x), ncol = a.r_pad / C::BN;
   const int m0 = (t / ncol) * C::BM, n0 = (t % ncol) * C::BN;
   floatx16 acc[C::TM][C::TN];
   bf16_mainloop<C>(a, m0, n0, acc, smem);
-
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int wy = wave / C::WN, wx = wave % C::WN;
-  const float dt = a.dt[a.t], zeta = a.zeta[a.t];
-#pragma unroll
-  for (int i = 0; i < C::TM; ++i)
-#pragma unroll
-    for (int g = 0; g < 4; ++g) {
-      const int row = m0 + wy * C::WTM + i * 32 + g * 8 + (lane / 32) * 4;
-      floatx4 h4 = {0.f, 0.f, 0.f, 0.f};
-      if (a.h) h4 = *reinterpret_cast<const floatx4 *>(a.h + row);
-#pragma unroll
-      for (int j = 0; j < C::TN; ++j) {
-        const int col = n0 + wx * C::WTN + j * 32 + (lane % 32);
-        const size_t off = (size_t)col * a.ld + row;
-        const floatx4 q4 = *reinterpret_cast<const floatx4 *>(a.q_in + off);
-        const floatx4 p4 = *reinterpret_cast<const floatx4 *>(a.p_in + off);
-        floatx4 qn, pn;
-        uint32_t b0[4], b1[4], b2[4];
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          float qv, pv;
-          update_b<ORDER, WALL>(q4[v], p4[v], acc[i][j][4 * g + v] + h4[v], dt, zeta, a.k,
-                                a.inv_m, a.qmax, a.pmax, qv, pv);
-          qn[v] = qv;
-          pn[v] = pv;
-          b0[v] = bf16_bits(qv);
-          if (C::QP == 3) {
-            const float r1 = qv - bf16_to_f32(b0[v]);  // exact
-            b1[v] = bf16_bits(r1);
-            const float r2 = r1 - bf16_to_f32(b1[v]);  // exact
-            b2[v] = bf16_bits(r2);
-          }
-        }
-        *reinterpret_cast<floatx4 *>(a.q_out + off) = qn;
-        *reinterpret_cast<floatx4 *>(a.p_out + off) = pn;
-        uint16_t *qb = a.qb_out + off;
-        *reinterpret_cast<uintx2 *>(qb) = uintx2{b0[0] | (b0[1] << 16), b0[2] | (b0[3] << 16)};
-        if (C::QP == 3) {
-          *reinterpret_cast<uintx2 *>(qb + a.plane_stride) =
-              uintx2{b1[0] | (b1[1] << 16), b1[2] | (b1[3] << 16)};
-          *reinterpret_cast<uintx2 *>(qb + 2 * a.plane_stride) =
-              uintx2{b2[0] | (b2[1] << 16), b2[2] | (b2[3] << 16)};
-        }
-      }
-    }
+  float *tile = reinterpret_cast<float *>(smem);
+  bf16_put<C>(tile, T::LD, acc);
+  floatx4 q4[T::CPT], p4[T::CPT];
+  EpiArgs e;
+  e.q_in = a.q_in;
+  e.p_in = a.p_in;
+  e.ld = a.ld;
+  e.m0 = m0;
+  e.n0 = n0;
+  epi_load<T>(e, q4, p4);
+  __syncthreads();
+  bf16_update<T, C::QP, ORDER, WALL>(a, m0, n0, tile, q4, p4);
 }
 
 // One BM x BN output tile of one step on the direct-to-LDS pipeline: the
@@ -459,75 +460,30 @@ __global__ __launch_bounds__(C::NT) void step_bf16_kernel(BStepArgs a) {
 // batched kernels.
 template <class C, int ORDER, int WALL>
 __device__ __forceinline__ void bf16_dma_tile(const BStepArgs &a, int m0, int n0, uint8_t *smem) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int wy = wave / C::WN, wx = wave % C::WN;
-  // State of this lane's outputs.  It is loaded before the contraction, so
-  // that its latency overlaps the matrix work, when the registers allow:
-  // for wave tiles of at most two MFMA blocks, or when a single four-wave
-  // group fills the CU's LDS (one wave per SIMD owns the whole register
-  // file).  Otherwise it is loaded afterwards (32 registers per block would
-  // stay live through the main loop).
-  constexpr bool PREFETCH = C::TM * C::TN <= 2 || (C::NW == 4 && C::LDS_BYTES > 80 * 1024);
-  floatx4 q4[C::TM][4][C::TN], p4[C::TM][4][C::TN], h4[C::TM][4];
-  auto load_state = [&]() {
-#pragma unroll
-    for (int i = 0; i < C::TM; ++i)
-#pragma unroll
-      for (int g = 0; g < 4; ++g) {
-        const int row = m0 + wy * C::WTM + i * 32 + g * 8 + (lane / 32) * 4;
-        h4[i][g] = floatx4{0.f, 0.f, 0.f, 0.f};
-        if (a.h) h4[i][g] = *reinterpret_cast<const floatx4 *>(a.h + row);
-#pragma unroll
-        for (int j = 0; j < C::TN; ++j) {
-          const size_t off = (size_t)(n0 + wx * C::WTN + j * 32 + (lane % 32)) * a.ld + row;
-          q4[i][g][j] = *reinterpret_cast<const floatx4 *>(a.q_in + off);
-          p4[i][g][j] = *reinterpret_cast<const floatx4 *>(a.p_in + off);
-        }
-      }
-  };
-  if constexpr (PREFETCH) load_state();
+  using T = EpiTile<C::BM, C::BN, C::NT>;
+  static_assert(T::BYTES <= C::LDS_BYTES, "the update tile fits in the main loop's LDS");
+  // State of this thread's chunks.  It is loaded before the contraction, so
+  // that its latency overlaps the matrix work, when the registers allow: for
+  // at most eight chunks per thread, or when a single four-wave group fills
+  // the CU's LDS (one wave per SIMD owns the whole register file).
+  // Otherwise it is loaded afterwards (eight registers per chunk would stay
+  // live through the main loop).
+  constexpr bool PREFETCH = T::CPT <= 8 || (C::NW == 4 && C::LDS_BYTES > 80 * 1024);
+  floatx4 q4[T::CPT], p4[T::CPT];
+  EpiArgs e;
+  e.q_in = a.q_in;
+  e.p_in = a.p_in;
+  e.ld = a.ld;
+  e.m0 = m0;
+  e.n0 = n0;
+  if constexpr (PREFETCH) epi_load<T>(e, q4, p4);
   floatx16 acc[C::TM][C::TN];
   bf16_mainloop_dma<C>(a, m0, n0, acc, smem);
-  if constexpr (!PREFETCH) load_state();
-
-  const float dt = a.dt[a.t], zeta = a.zeta[a.t];
-#pragma unroll
-  for (int i = 0; i < C::TM; ++i)
-#pragma unroll
-    for (int g = 0; g < 4; ++g) {
-      const int row = m0 + wy * C::WTM + i * 32 + g * 8 + (lane / 32) * 4;
-#pragma unroll
-      for (int j = 0; j < C::TN; ++j) {
-        const size_t off = (size_t)(n0 + wx * C::WTN + j * 32 + (lane % 32)) * a.ld + row;
-        floatx4 qn, pn;
-        uint32_t b0[4], b1[4], b2[4];
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          float qv, pv;
-          update_b<ORDER, WALL>(q4[i][g][j][v], p4[i][g][j][v], acc[i][j][4 * g + v] + h4[i][g][v],
-                                dt, zeta, a.k, a.inv_m, a.qmax, a.pmax, qv, pv);
-          qn[v] = qv;
-          pn[v] = pv;
-          b0[v] = bf16_bits(qv);
-          if (C::QP == 3) {
-            const float r1 = qv - bf16_to_f32(b0[v]);  // exact
-            b1[v] = bf16_bits(r1);
-            const float r2 = r1 - bf16_to_f32(b1[v]);  // exact
-            b2[v] = bf16_bits(r2);
-          }
-        }
-        *reinterpret_cast<floatx4 *>(a.q_out + off) = qn;
-        *reinterpret_cast<floatx4 *>(a.p_out + off) = pn;
-        uint16_t *qb = a.qb_out + off;
-        *reinterpret_cast<uintx2 *>(qb) = uintx2{b0[0] | (b0[1] << 16), b0[2] | (b0[3] << 16)};
-        if (C::QP == 3) {
-          *reinterpret_cast<uintx2 *>(qb + a.plane_stride) =
-              uintx2{b1[0] | (b1[1] << 16), b1[2] | (b1[3] << 16)};
-          *reinterpret_cast<uintx2 *>(qb + 2 * a.plane_stride) =
-              uintx2{b2[0] | (b2[1] << 16), b2[2] | (b2[3] << 16)};
-        }
-      }
-    }
+  float *tile = reinterpret_cast<float *>(smem);
+  bf16_put<C>(tile, T::LD, acc);
+  if constexpr (!PREFETCH) epi_load<T>(e, q4, p4);
+  __syncthreads();
+  bf16_update<T, C::QP, ORDER, WALL>(a, m0, n0, tile, q4, p4);
 }
 
 template <class C, int ORDER, int WALL>
@@ -559,12 +515,14 @@ __global__ __launch_bounds__(BatchFp8Cfg::NT) void step_batch_bf16_kernel(
   BStepArgs a = base;
   a.Ja = d.Ja;
   a.Jb = d.Jb;
-  a.q_in = d.q[cur];
-  a.p_in = d.p[cur];
-  a.q_out = d.q[cur ^ 1];
-  a.p_out = d.p[cur ^ 1];
-  a.qb_in = d.qb[cur];
-  a.qb_out = d.qb[cur ^ 1];
+  // buffer parity by selection (a run-time index into the local copy of the
+  // descriptor would place it in scratch memory)
+  a.q_in = cur ? d.q[1] : d.q[0];
+  a.p_in = cur ? d.p[1] : d.p[0];
+  a.q_out = cur ? d.q[0] : d.q[1];
+  a.p_out = cur ? d.p[0] : d.p[1];
+  a.qb_in = cur ? d.qb[1] : d.qb[0];
+  a.qb_out = cur ? d.qb[0] : d.qb[1];
   a.ld = d.n_pad;
   a.n_pad = d.n_pad;
   a.plane_stride = (int64_t)d.n_pad * base.r_pad;

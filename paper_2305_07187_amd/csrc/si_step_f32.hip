@@ -21,28 +21,10 @@
 // kk+4g .. kk+4g+3 with one 128-bit LDS load per operand and MFMA s uses the
 // s-th of them; each index is summed exactly once, in increasing kk order,
 // so the permutation only changes which lane holds which index.
+#include "si_epilogue.h"
 #include "si_f32_gemm.h"
 
 namespace si {
-
-// Eq. (8) + walls for one element.  f is sum_j J_ij q_j (+ h_i).
-template <int ORDER, int WALL>
-__device__ __forceinline__ void update(float q, float p, float f, float dt, float zeta,
-                                       float k, float inv_m, float qmax, float pmax,
-                                       float &qn, float &pn) {
-  const float c = dt * inv_m;
-  // force of Eq. (4) with q0 = 0, coupling weighted by zeta_n
-  const float force = fmaf(zeta, f, -k * q);
-  const float v = fmaf(dt, force, p);
-  pn = fminf(fmaxf(v, -pmax), pmax);
-  float u;
-  if (ORDER == SI_ORDER_PAPER)
-    u = fmaf(c, p, q);   // q(n+1) = q(n) + (Delta/m) p(n)
-  else
-    u = fmaf(c, pn, q);  // symplectic variant: moves with the new p
-  qn = fminf(fmaxf(u, -qmax), qmax);
-  if (WALL == SI_WALL_INELASTIC && fabsf(u) > qmax) pn = 0.f;
-}
 
 // Contraction length for n spins: n rounded up to the slab depth.  Columns
 // of J beyond n are zero padding, so stopping there drops only exact zeros.
@@ -61,28 +43,28 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, const float *__rest
                                           const float *__restrict__ p_in, float *__restrict__ q_out,
                                           float *__restrict__ p_out, int ld, int K, int m0, int n0,
                                           float *smem) {
+  using T = EpiTile<C::BM, C::BN, C::NT>;
+  static_assert(T::BYTES <= C::LDS_FLOATS * 4, "the update tile fits in the main loop's LDS");
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int wy = wave / C::WN, wx = wave % C::WN;
   constexpr int G = C::M::NACC / 4;
-  // The state this lane updates is loaded before the contraction so that
+  EpiArgs e;
+  e.q_in = q_in;
+  e.p_in = p_in;
+  e.h = a.h;
+  e.q_out = q_out;
+  e.p_out = p_out;
+  e.qb_out = nullptr;
+  e.plane_stride = 0;
+  e.mask_out = a.mask_out;
+  e.ld = ld;
+  e.m0 = m0;
+  e.n0 = n0;
+  // The state this thread updates is loaded before the contraction so that
   // its latency overlaps the matrix work.
-  floatx4 q4[C::TM][G][C::TN], p4[C::TM][G][C::TN], h4[C::TM][G];
-#pragma unroll
-  for (int i = 0; i < C::TM; ++i)
-#pragma unroll
-    for (int g = 0; g < G; ++g) {
-      const int row = m0 + wy * C::WTM + i * C::MB + g * 8 + (lane / C::MB) * 4;
-      h4[i][g] = floatx4{0.f, 0.f, 0.f, 0.f};
-      if (a.h) h4[i][g] = *reinterpret_cast<const floatx4 *>(a.h + row);
-#pragma unroll
-      for (int j = 0; j < C::TN; ++j) {
-        const int col = n0 + wx * C::WTN + j * C::MB + (lane % C::MB);
-        const size_t off = (size_t)col * ld + row;
-        q4[i][g][j] = *reinterpret_cast<const floatx4 *>(q_in + off);
-        p4[i][g][j] = *reinterpret_cast<const floatx4 *>(p_in + off);
-      }
-    }
+  floatx4 q4[T::CPT], p4[T::CPT];
+  epi_load<T>(e, q4, p4);
 
   typename C::acc_t acc[C::TM][C::TN];
   if constexpr (C::STAGES > 0)
@@ -90,41 +72,24 @@ __device__ __forceinline__ void step_tile(const StepArgs &a, const float *__rest
   else
     f32_mainloop<C, B_PLAIN>(Jm, q_in, ld, K, m0, n0, acc, smem);
 
-  const float dt = a.dt[a.t], zeta = a.zeta[a.t];
+  // F through LDS into the state's layout (the main loop has released it)
 #pragma unroll
-  for (int i = 0; i < C::TM; ++i) {
+  for (int i = 0; i < C::TM; ++i)
 #pragma unroll
-    for (int g = 0; g < G; ++g) {
-      const int row = m0 + wy * C::WTM + i * C::MB + g * 8 + (lane / C::MB) * 4;
+    for (int g = 0; g < G; ++g)
 #pragma unroll
-      for (int j = 0; j < C::TN; ++j) {
-        const int col = n0 + wx * C::WTN + j * C::MB + (lane % C::MB);
-        const size_t off = (size_t)col * ld + row;
-        floatx4 qn, pn;
-        uint32_t mk = 0;
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          float qv, pv;
-          update<ORDER, WALL>(q4[i][g][j][v], p4[i][g][j][v], acc[i][j][4 * g + v] + h4[i][g][v],
-                              dt, zeta, a.k, a.inv_m, a.qmax, a.pmax, qv, pv);
-          qn[v] = qv;
-          pn[v] = pv;
-          if (a.mask_out) {
-            // the unclamped values, recomputed exactly as in update()
-            const float c = dt * a.inv_m;
-            const float force = fmaf(zeta, acc[i][j][4 * g + v] + h4[i][g][v], -a.k * q4[i][g][j][v]);
-            const float vv = fmaf(dt, force, p4[i][g][j][v]);
-            const float uu = fmaf(c, p4[i][g][j][v], q4[i][g][j][v]);
-            const uint32_t bits = (fabsf(uu) <= a.qmax ? 1u : 0u) | (fabsf(vv) <= a.pmax ? 2u : 0u);
-            mk |= bits << (8 * v);
-          }
-        }
-        *reinterpret_cast<floatx4 *>(q_out + off) = qn;
-        *reinterpret_cast<floatx4 *>(p_out + off) = pn;
-        if (a.mask_out) *reinterpret_cast<uint32_t *>(a.mask_out + off) = mk;
-      }
-    }
-  }
+      for (int j = 0; j < C::TN; ++j)
+        epi_put(smem, T::LD, wy * C::WTM + i * C::MB + g * 8 + (lane / C::MB) * 4,
+                wx * C::WTN + j * C::MB + (lane % C::MB), acc[i][j][4 * g], acc[i][j][4 * g + 1],
+                acc[i][j][4 * g + 2], acc[i][j][4 * g + 3]);
+  __syncthreads();
+  e.dt = a.dt[a.t];
+  e.zeta = a.zeta[a.t];
+  e.k = a.k;
+  e.inv_m = a.inv_m;
+  e.qmax = a.qmax;
+  e.pmax = a.pmax;
+  epi_apply<T, ORDER, WALL, 0>(smem, e, q4, p4);
 }
 
 template <class C, int ORDER, int WALL>
@@ -225,7 +190,7 @@ __global__ __launch_bounds__(C::NT) void resident_f32_kernel(StepArgs a, Residen
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             float qv, pv;
-            update<ORDER, WALL>(q4[i][g][j][v], p4[i][g][j][v], acc[i][j][4 * g + v] + h4[i][g][v],
+            spring_update<ORDER, WALL>(q4[i][g][j][v], p4[i][g][j][v], acc[i][j][4 * g + v] + h4[i][g][v],
                                 dt, zeta, a.k, a.inv_m, a.qmax, a.pmax, qv, pv);
             q4[i][g][j][v] = qv;
             p4[i][g][j][v] = pv;
