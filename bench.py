@@ -19,7 +19,8 @@ HIP events on the stream the kernels run on) and its time-to-target is the
 event time of the first check with a replica at or below the target.
 The batched configuration (256 uneven instances, R = 64) is timed per step
 in FP32 and in the BF16 form, and against the same instances stepped one
-after another.
+after another; the differentiation configuration (schedule gradient at
+N = 2000, R = 64, 2000 steps) is timed beside its plain forward run.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
 """
@@ -124,6 +125,46 @@ def batched_form(si, steps=300, n_inst=256, r=64):
     out["batched_vs_sequential_fp32"] = seq * 1000.0 / out["fp32_batched_ms_per_step"]
     out["bf16_vs_fp32_batched"] = (out["fp32_batched_ms_per_step"] /
                                    out["bf16x_mixedj_batched_ms_per_step"])
+    return out
+
+
+def differentiation_form(si, n=2000, r=64, steps=2000, ckpt=100, repeats=3):
+    """The differentiation configuration: gradient of the mean relaxed
+    end-energy with respect to the 2000-entry Delta and zeta schedules at
+    N = 2000, R = 64 (checkpoints every 100 steps), timed end to end on the
+    stream (forward with checkpoints, per-segment recomputation, backward),
+    beside the plain forward run of the same length."""
+    import torch
+
+    from paper_2305_07187_amd import instances
+    dev = torch.device("cuda:0")
+    J = instances.make_J_torch(n, "pm1", 0, device=dev)
+    x0 = instances.make_x0_torch(n, r, 0, device=dev)
+    stream = torch.cuda.current_stream()
+    m = si.SpringIsing(J, x0, total_steps=steps)
+    m.relaxed_energy_grad(ckpt)  # warm-up
+    grad_ms, fwd_ms = [], []
+    for _ in range(repeats):
+        a, b, c = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        m.set_state(x0, None, 0)
+        a.record(stream)
+        m.run(steps)
+        b.record(stream)
+        m.set_state(x0, None, 0)
+        torch.cuda.synchronize()
+        c0 = torch.cuda.Event(enable_timing=True)
+        c0.record(stream)
+        loss, gd, gz = m.relaxed_energy_grad(ckpt)
+        c.record(stream)
+        torch.cuda.synchronize()
+        fwd_ms.append(a.elapsed_time(b))
+        grad_ms.append(c0.elapsed_time(c))
+    out = {"workload": f"N={n} +-1, R={r}, {steps}-step schedule, checkpoint every {ckpt}",
+           "kernel": m.info()["kernel_name"], "gradient_ms": min(grad_ms),
+           "forward_ms": min(fwd_ms), "gradient_over_forward": min(grad_ms) / min(fwd_ms),
+           "loss": float(loss.cpu()[0]), "finite": bool(torch.isfinite(gd).all() and
+                                                      torch.isfinite(gz).all())}
+    m.close()
     return out
 
 
@@ -302,6 +343,7 @@ def main():
     model.close()
     if fp32_line and not args.no_batched and (n, r, args.couplings) == (N, R, "pm1"):
         out["batched_form"] = batched_form(si)
+        out["differentiation_form"] = differentiation_form(si)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out))

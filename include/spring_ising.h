@@ -197,6 +197,21 @@ si_status spring_ising_run(si_ctx *ctx, int32_t n_steps);
  * Results are bit-identical to direct launches.  0 turns graphs off. */
 si_status spring_ising_set_graph(si_ctx *ctx, int32_t min_steps);
 
+/* Split the contraction of the coupling product over k: ksplit ranges are
+ * multiplied in parallel into a device workspace (ksplit x the state's size)
+ * and a second launch adds them in a fixed order and applies Eq. (8).  This
+ * gives problems with fewer output tiles than CUs (few replicas, e.g. the
+ * adjoint's R = 64) enough workgroups.  0 (the default) chooses
+ * automatically: a split only when the tile is chosen automatically and its
+ * tiles number fewer than the CUs, enough ranges (at most 8, each at least
+ * 128 deep) to give every CU two workgroups; the adjoint's backward product
+ * follows the same rule for its 32 x 32 tiles.  1 turns the split off; 2..16
+ * force it.  Results are deterministic, but the split changes the order of
+ * the FP32 sums (so trajectories differ from unsplit ones by rounding).
+ * SI_ERR_INVALID outside 0..16; SI_ERR_UNSUPPORTED for 2..16 on a batch, a
+ * BF16 form or a tile without a split form. */
+si_status spring_ising_set_ksplit(si_ctx *ctx, int32_t ksplit);
+
 /* Execute run() calls of at least min_steps steps as one resident launch
  * (FP32 single instance; the per-step loop of Eq. 8 moved onto the device):
  * every workgroup owns one output tile for the whole call and keeps that

@@ -51,9 +51,15 @@ struct StepArgs {
   int32_t order;      // si_order
   int32_t wall;       // si_wall
   uint8_t *mask_out;  // nullable: per element bit 0 = |u| <= qmax, bit 1 = |v| <= pmax
+  int32_t ksplit;     // >= 2: split contraction into ksplit ranges (workspace fsplit)
+  float *fsplit;      // [ksplit][r_pad][n_pad] partial products, or null
 };
 
 hipError_t launch_step_f32(int32_t tile, const StepArgs &a, hipStream_t s);
+// Split contraction (tiles listed in si_splitk.hip): partial products into
+// a.fsplit, then the update from their fixed-order sum.
+bool tile_has_split(int32_t tile);
+hipError_t launch_step_f32_split(int32_t tile, const StepArgs &a, hipStream_t s);
 
 // Resident form: one cooperative launch runs n_steps steps.  Every workgroup
 // owns one output tile for the whole launch and keeps that tile's q and p in
@@ -156,6 +162,15 @@ hipError_t launch_adj_step(const float *J, const float *lamq_in, const float *la
                            float *lamq_out, float *lamp_out, double *part, const float *dt,
                            const float *zeta, int32_t n, float k, float inv_m, int32_t n_pad,
                            int32_t r_pad, hipStream_t s);
+// Backward step with the split contraction; writes adj_split_groups()
+// partial triples to part.
+int32_t adj_split_groups(int32_t n_pad, int32_t r_pad);
+hipError_t launch_adj_step_split(const float *J, const float *lamq_in, const float *lamp_in,
+                                 const uint8_t *mask, const float *q_n, const float *p_n,
+                                 float *lamq_out, float *lamp_out, double *part, const float *dt,
+                                 const float *zeta, int32_t n, float k, float inv_m, int32_t n_pad,
+                                 int32_t n_spins, int32_t r_pad, int32_t ksplit, float *W,
+                                 hipStream_t s);
 // mode 0: loss[0] = -1/2 * sum(part[:,0]) / r_count;  mode 1: gradient entries
 // g_dt[n], g_zeta[n] from the three partial sums of step n.
 hipError_t launch_adj_reduce(const double *part, int32_t nwg, int32_t mode, double *loss,

@@ -125,6 +125,11 @@ struct si_ctx {
   // resident launches of run(n): n >= resident_min_steps (0: off)
   int32_t resident_min_steps = 0;
   int32_t resident_tile = -1, resident_per_cu = 0;  // occupancy cache for `tile`
+  // split contraction: 0 = automatic, >= 1 = forced number of k ranges
+  int32_t ksplit_mode = 0;
+  int32_t user_tile = 0;        // tile requested at init (0: automatic)
+  float *fsplit = nullptr;      // partial products of the split contraction
+  int64_t fsplit_cap = 0;       // floats
   int32_t *res_sync = nullptr;  // [0] time-out flag, [64 ..] per-group step counts
   int32_t res_sync_cap = 0;
   hipStream_t cap_stream = nullptr;
@@ -208,6 +213,47 @@ static si_status check_params(const si_params *p) {
 // such tile, the one with the most workgroups (small problems).
 static TileShape shape_of(int32_t precision, int32_t tile) {
   return precision == SI_PREC_FP32 ? tile_shape(tile) : tile_shape_bf16(tile);
+}
+
+// Number of contraction ranges for a problem whose output has fewer
+// workgroups (`tiles`) than there are CUs: enough to give every CU two (at
+// most 8 ranges), each range at least four 32-deep slabs long.  (At N=2000,
+// R=64 on MI355X: 32x32 tiles, 4 ranges, 12.4 us per step against 26.9 us
+// unsplit and 17.8 us with 2 ranges.)
+static int32_t auto_split(int64_t tiles, int32_t n, int num_cus) {
+  if (tiles >= num_cus) return 1;
+  int64_t s = (2 * (int64_t)num_cus + tiles - 1) / tiles;
+  if (s > 8) s = 8;
+  const int64_t smax = round_up(n, 32) / 128;
+  if (s > smax) s = smax;
+  return s < 1 ? 1 : (int32_t)s;
+}
+
+// Split of the FP32 step for tile `tile` in this context (1: none).
+static int32_t split_for(const si_ctx *c, int32_t tile) {
+  if (c->n_inst || c->qplanes || !tile_has_split(tile)) return 1;
+  if (c->ksplit_mode >= 1) return c->ksplit_mode;
+  if (c->user_tile != 0) return 1;
+  const TileShape ts = tile_shape(tile);
+  return auto_split((int64_t)(c->n_pad / ts.bm) * (c->r_pad / ts.bn), c->n, c->num_cus);
+}
+
+// Split of the adjoint's backward product (32 x 32 tiles).
+static int32_t adj_split(const si_ctx *c) {
+  if (c->ksplit_mode >= 1) return c->ksplit_mode;
+  return auto_split((int64_t)(c->n_pad / ADJ_BM) * (c->r_pad / ADJ_BN), c->n, c->num_cus);
+}
+
+// Workspace for the split contraction of the current tile and of the
+// adjoint (allocated here, never while a launch sequence is captured).
+static hipError_t ensure_split_ws(si_ctx *c, bool adjoint = false) {
+  const int64_t NR = (int64_t)c->n_pad * c->r_pad;
+  int64_t need = split_for(c, c->tile) > 1 ? split_for(c, c->tile) * NR : 0;
+  if (adjoint && adj_split(c) > 1 && adj_split(c) * NR > need) need = adj_split(c) * NR;
+  if (need <= c->fsplit_cap) return hipSuccess;
+  hipError_t e = c->alloc(&c->fsplit, need);
+  if (e == hipSuccess) c->fsplit_cap = need;
+  return e;
 }
 
 static int32_t choose_tile_bf16(int32_t n, int32_t r, int num_cus, int32_t precision) {
@@ -342,6 +388,7 @@ si_status spring_ising_init(si_ctx **out, int32_t n, int32_t r, const float *J, 
   prm = &c->prm;
 
   const bool lowp = prm->precision != SI_PREC_FP32;
+  c->user_tile = prm->tile;
   c->tile = prm->tile ? prm->tile
                       : (lowp ? choose_tile_bf16(n, r, c->num_cus, prm->precision)
                               : choose_tile(n, r, c->num_cus));
@@ -390,6 +437,7 @@ si_status spring_ising_init(si_ctx **out, int32_t n, int32_t r, const float *J, 
   INIT_HIP(launch_pack_state(p0, n, r, c->p[0], c->n_pad, c->r_pad, c->stream));
   if (lowp) INIT_HIP(launch_split_planes(c->q[0], c->qb[0], nr, c->qplanes, c->stream));
   INIT_HIP(launch_zero_i32(c->eacc, c->r_pad, c->stream));
+  INIT_HIP(ensure_split_ws(c));
   build_schedules(*prm, c->host_dt, c->host_zeta);
   INIT_HIP(hipMemcpyAsync(c->dt, c->host_dt.data(), sizeof(float) * prm->total_steps,
                           hipMemcpyHostToDevice, c->stream));
@@ -688,8 +736,11 @@ static StepArgs step_args(si_ctx *c) {
   a.order = c->prm.order;
   a.wall = c->prm.wall;
   a.mask_out = nullptr;
+  a.ksplit = split_for(c, c->tile);
+  a.fsplit = c->fsplit;
   return a;
 }
+
 
 static si_status do_steps_batch(si_ctx *c, int32_t n_steps) {
   if (c->b_lowp) {
@@ -743,6 +794,10 @@ static si_status do_steps(si_ctx *c, int32_t n_steps) {
   a.pmax = c->prm.pmax;
   a.order = c->prm.order;
   a.wall = c->prm.wall;
+  a.ksplit = split_for(c, c->tile);
+  a.fsplit = c->fsplit;
+  if (a.ksplit > 1 && (int64_t)a.ksplit * c->n_pad * c->r_pad > c->fsplit_cap)
+    return fail(SI_ERR_STATE, "step: split-contraction workspace missing");
   for (int32_t s = 0; s < n_steps; ++s) {
     a.q_in = c->q[c->cur];
     a.p_in = c->p[c->cur];
@@ -770,7 +825,10 @@ si_status spring_ising_relaxed_energy_grad(si_ctx *c, int32_t ckpt_every, double
   const int32_t S = c->prm.total_steps, t0 = c->t, C = ckpt_every;
   const int32_t nseg = (S - t0 + C - 1) / C;
   const int64_t NR = (int64_t)c->n_pad * c->r_pad;
-  const int32_t nwg = (c->n_pad / ADJ_BM) * (c->r_pad / ADJ_BN);
+  const int32_t asplit = adj_split(c);
+  const int32_t nwg_seed = (c->n_pad / ADJ_BM) * (c->r_pad / ADJ_BN);
+  const int32_t nwg = asplit > 1 ? adj_split_groups(c->n_pad, c->r_pad) : nwg_seed;
+  SI_HIP(c, ensure_split_ws(c, true));
   if ((int64_t)nseg * 2 * NR > c->adj_ckpt_cap) {
     SI_HIP(c, c->alloc(&c->adj_ckpt, (int64_t)(nseg > 0 ? nseg : 1) * 2 * NR));
     c->adj_ckpt_cap = (int64_t)(nseg > 0 ? nseg : 1) * 2 * NR;
@@ -782,7 +840,8 @@ si_status spring_ising_relaxed_energy_grad(si_ctx *c, int32_t ckpt_every, double
   }
   if (!c->adj_lam) {
     SI_HIP(c, c->alloc(&c->adj_lam, 4 * NR));
-    SI_HIP(c, c->alloc(&c->adj_part, (int64_t)nwg * 3));
+    const int32_t groups = nwg > nwg_seed ? nwg : nwg_seed;
+    SI_HIP(c, c->alloc(&c->adj_part, (int64_t)(groups > 1024 ? groups : 1024) * 3));
   }
   const float inv_r = 1.0f / (float)c->r, inv_m = 1.0f / c->prm.m, k = c->prm.k;
   SI_HIP(c, launch_fill_f64(g_dt, S, 0.0, c->stream));
@@ -804,8 +863,8 @@ si_status spring_ising_relaxed_energy_grad(si_ctx *c, int32_t ckpt_every, double
   int lc = 0;
   SI_HIP(c, launch_adj_seed(c->J, c->q[c->cur], lam[0][0], lam[0][1], c->adj_part, c->n_pad,
                             c->r_pad, inv_r, c->stream));
-  SI_HIP(c, launch_adj_reduce(c->adj_part, nwg, 0, loss, nullptr, nullptr, c->dt, c->zeta, 0, k,
-                              inv_m, c->r, c->stream));
+  SI_HIP(c, launch_adj_reduce(c->adj_part, nwg_seed, 0, loss, nullptr, nullptr, c->dt, c->zeta, 0,
+                              k, inv_m, c->r, c->stream));
   // reverse sweep, one segment at a time
   StepArgs a = step_args(c);
   for (int32_t sg = nseg - 1; sg >= 0; --sg) {
@@ -826,10 +885,16 @@ si_status spring_ising_relaxed_energy_grad(si_ctx *c, int32_t ckpt_every, double
     }
     for (int32_t j = len - 1; j >= 0; --j) {
       const int32_t n = t_a + j;
-      SI_HIP(c, launch_adj_step(c->J, lam[lc][0], lam[lc][1], c->adj_mask + (int64_t)j * NR,
-                                sq + 2 * j * NR, sq + 2 * j * NR + NR, lam[lc ^ 1][0],
-                                lam[lc ^ 1][1], c->adj_part, c->dt, c->zeta, n, k, inv_m,
-                                c->n_pad, c->r_pad, c->stream));
+      if (asplit > 1)
+        SI_HIP(c, launch_adj_step_split(c->J, lam[lc][0], lam[lc][1], c->adj_mask + (int64_t)j * NR,
+                                        sq + 2 * j * NR, sq + 2 * j * NR + NR, lam[lc ^ 1][0],
+                                        lam[lc ^ 1][1], c->adj_part, c->dt, c->zeta, n, k, inv_m,
+                                        c->n_pad, c->n, c->r_pad, asplit, c->fsplit, c->stream));
+      else
+        SI_HIP(c, launch_adj_step(c->J, lam[lc][0], lam[lc][1], c->adj_mask + (int64_t)j * NR,
+                                  sq + 2 * j * NR, sq + 2 * j * NR + NR, lam[lc ^ 1][0],
+                                  lam[lc ^ 1][1], c->adj_part, c->dt, c->zeta, n, k, inv_m,
+                                  c->n_pad, c->r_pad, c->stream));
       SI_HIP(c, launch_adj_reduce(c->adj_part, nwg, 1, nullptr, g_dt, g_zeta, c->dt, c->zeta, n,
                                   k, inv_m, c->r, c->stream));
       lc ^= 1;
@@ -883,7 +948,7 @@ static si_status run_graph(si_ctx *c, int32_t n_steps) {
 // Workgroups of the resident launch for the current tile, or 0 when the
 // context has no resident form or they do not all fit on the device.
 static int32_t resident_groups(si_ctx *c) {
-  if (c->n_inst || c->qplanes) return 0;
+  if (c->n_inst || c->qplanes || split_for(c, c->tile) > 1) return 0;
   if (c->resident_tile != c->tile) {
     int per = 0;
     if (resident_f32_groups_per_cu(c->tile, c->prm.order, c->prm.wall, &per) != hipSuccess)
@@ -943,6 +1008,18 @@ si_status spring_ising_run(si_ctx *c, int32_t n_steps) {
   return do_steps(c, n_steps);
 }
 
+si_status spring_ising_set_ksplit(si_ctx *c, int32_t ksplit) {
+  SI_USABLE(c);
+  if (ksplit < 0 || ksplit > 16) return fail(SI_ERR_INVALID, "set_ksplit: ksplit=%d not in 0..16", ksplit);
+  if (ksplit >= 2 && (c->n_inst || c->qplanes || !tile_has_split(c->tile)))
+    return fail(SI_ERR_UNSUPPORTED, "set_ksplit: the split contraction needs a single FP32 "
+                "instance on a tile with a split form (tile %d)", c->tile);
+  c->ksplit_mode = ksplit;
+  SI_HIP(c, ensure_split_ws(c));
+  c->drop_graphs();
+  return SI_OK;
+}
+
 si_status spring_ising_set_resident(si_ctx *c, int32_t min_steps) {
   SI_USABLE(c);
   if (min_steps < 0) return fail(SI_ERR_INVALID, "set_resident: min_steps < 0");
@@ -995,6 +1072,10 @@ si_status spring_ising_autotune(si_ctx *c, int32_t steps, int32_t *best_tile, fl
     const TileShape ts = shape_of(c->prm.precision, tile);
     if (c->n_pad % ts.bm || c->r_pad % ts.bn) continue;
     c->tile = tile;
+    if (ensure_split_ws(c) != hipSuccess) {
+      (void)hipGetLastError();
+      continue;
+    }
     si_status st = do_steps(c, 1);  // warm-up (also loads the code object)
     if (st == SI_OK) {
       SI_HIP(c, hipEventRecord(e0, c->stream));
@@ -1249,6 +1330,9 @@ si_status spring_ising_info(si_ctx *c, si_info *info) {
   if (c->n_inst)
     snprintf(info->kernel_name, sizeof info->kernel_name, "step_batch_%s_%dx%d_x%d",
              c->b_lowp ? "bf16" : "f32", BATCH_BM, BATCH_BN, c->n_inst);
+  else if (split_for(c, c->tile) > 1)
+    snprintf(info->kernel_name, sizeof info->kernel_name, "%s_ks%d",
+             shape_of(c->prm.precision, c->tile).name, split_for(c, c->tile));
   else
     snprintf(info->kernel_name, sizeof info->kernel_name, "%s",
              shape_of(c->prm.precision, c->tile).name);

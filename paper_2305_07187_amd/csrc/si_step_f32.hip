@@ -230,44 +230,6 @@ __global__ __launch_bounds__(C::NT) void step_batch_f32_kernel(StepArgs a,
                             it.z * C::BN, smem);
 }
 
-// Tile table: id, BM, BN, waves (WM x WN), MFMA block edge, slab depth BK,
-// LDS stages (0: register-staged double buffer; >= 3: direct-to-LDS ring).
-#define SI_F32_TILES(X)                \
-  X(1, 64, 128, 2, 2, 32, 32, 0, 1)    \
-  X(2, 64, 64, 2, 2, 32, 32, 0, 1)        \
-  X(3, 32, 32, 2, 2, 16, 32, 0, 1)        \
-  X(4, 128, 64, 2, 2, 32, 32, 0, 1)       \
-  X(5, 128, 128, 2, 2, 32, 32, 0, 1)      \
-  X(6, 32, 64, 2, 2, 16, 32, 0, 1)        \
-  X(7, 64, 128, 2, 2, 32, 64, 0, 1)       \
-  X(8, 64, 128, 2, 4, 32, 32, 0, 1)       \
-  X(9, 64, 64, 2, 2, 32, 64, 0, 1)        \
-  X(10, 64, 128, 2, 2, 16, 32, 0, 1)      \
-  X(11, 128, 128, 2, 4, 32, 32, 0, 1)     \
-  X(12, 64, 64, 2, 2, 16, 32, 0, 1)       \
-  X(13, 64, 64, 2, 2, 32, 32, 3, 1)       \
-  X(14, 64, 64, 2, 2, 32, 32, 4, 1)       \
-  X(15, 64, 64, 2, 2, 32, 64, 3, 1)       \
-  X(16, 64, 128, 2, 2, 32, 32, 4, 1)      \
-  X(17, 64, 64, 2, 2, 32, 32, 6, 1)       \
-  X(18, 128, 64, 2, 2, 32, 32, 4, 1)      \
-  X(19, 64, 64, 2, 2, 32, 32, 4, 2)    \
-  X(20, 64, 64, 2, 2, 32, 32, 4, 4)    \
-  X(21, 64, 64, 2, 1, 32, 32, 4, 1)    \
-  X(22, 64, 64, 2, 1, 32, 32, 4, 2)    \
-  X(23, 64, 64, 2, 2, 32, 64, 3, 2)    \
-  X(24, 64, 128, 2, 2, 32, 32, 4, 2)   \
-  X(25, 128, 64, 4, 2, 32, 32, 0, 1)   \
-  X(26, 128, 64, 4, 2, 32, 32, 4, 1)   \
-  X(27, 64, 128, 2, 4, 32, 32, 4, 1)   \
-  X(28, 128, 64, 4, 2, 32, 64, 3, 1)   \
-  X(29, 128, 128, 4, 4, 32, 32, 0, 1)  \
-  X(30, 128, 64, 4, 2, 32, 32, 6, 1)   \
-  X(31, 128, 64, 4, 2, 32, 32, 4, 2)   \
-  X(32, 64, 128, 2, 4, 32, 32, 6, 1)   \
-  X(33, 128, 64, 4, 2, 32, 32, 5, 1)   \
-  X(34, 128, 64, 4, 2, 32, 32, 3, 1)
-
 TileShape tile_shape(int32_t tile) {
   switch (tile) {
 #define SI_SHAPE(id, bm, bn, wm, wn, mb, bk, st, ks) \
@@ -375,6 +337,7 @@ hipError_t launch_step_batch_f32(const StepArgs &a, const BatchDesc *descs, cons
 }
 
 hipError_t launch_step_f32(int32_t tile, const StepArgs &a, hipStream_t s) {
+  if (a.ksplit > 1) return launch_step_f32_split(tile, a, s);
   switch (tile) {
 #define SI_LAUNCH(id, bm, bn, wm, wn, mb, bk, st, ks) \
   case id:                                            \

@@ -91,6 +91,7 @@ _SIGNATURES = {
     "spring_ising_relaxed_energy_grad": [_P, _I, _P, _P, _P],
     "spring_ising_set_graph": [_P, _I],
     "spring_ising_set_resident": [_P, _I],
+    "spring_ising_set_ksplit": [_P, _I],
     "spring_ising_update_best": [_P],
     "spring_ising_get_best": [_P, _P, _P],
     "spring_ising_hamiltonian": [_P, _P],
@@ -274,6 +275,10 @@ def spring_ising_set_graph(ctx, min_steps):
 
 def spring_ising_set_resident(ctx, min_steps):
     _check(load_library().spring_ising_set_resident(ctx, int(min_steps)))
+
+
+def spring_ising_set_ksplit(ctx, ksplit):
+    _check(load_library().spring_ising_set_ksplit(ctx, int(ksplit)))
 
 
 def spring_ising_autotune(ctx, steps):
@@ -483,6 +488,9 @@ class SpringIsing:
 
     def set_resident(self, min_steps):
         spring_ising_set_resident(self.ctx, min_steps)
+
+    def set_ksplit(self, ksplit):
+        spring_ising_set_ksplit(self.ctx, ksplit)
 
     def autotune(self, steps=20):
         return spring_ising_autotune(self.ctx, steps)

@@ -58,7 +58,7 @@ def test_resident_variants_and_field(order, wall):
     res = []
     for resident in (0, 2):
         si = ensure_built()
-        m = si.SpringIsing(to_dev(J), to_dev(x0), total_steps=S, order=order, wall=wall)
+        m = si.SpringIsing(to_dev(J), to_dev(x0), total_steps=S, order=order, wall=wall, tile=3)
         m.set_field(h)
         m.set_resident(resident)
         m.run(S)
