@@ -291,11 +291,12 @@ static int32_t choose_tile_bf16(int32_t n, int32_t r, int num_cus, int32_t preci
 static int32_t choose_tile(int32_t n, int32_t r, int num_cus) {
   // Preference from tile sweeps on MI355X: at N=2000, R=1024 the 8-wave
   // direct-to-LDS tiles (128x64, then 64x128) lead; a problem with at least four
-  // 64x128 tiles per CU (N=8000, R=2048) runs best on the register-staged
-  // 64x128 tile.
+  // 64x128 tiles per CU and at least 128 replicas (N=8000, R=2048) runs best
+  // on the register-staged 64x128 tile.
   {
     const TileShape big = tile_shape(1);
-    if ((round_up(n, big.bm) / big.bm) * (round_up(r, big.bn) / big.bn) >= 4 * (int64_t)num_cus)
+    if (r >= big.bn &&
+        (round_up(n, big.bm) / big.bm) * (round_up(r, big.bn) / big.bn) >= 4 * (int64_t)num_cus)
       return 1;
   }
   const int32_t order[] = {26, 27, 2, 9, 12, 6, 3};
