@@ -262,12 +262,12 @@ static int32_t choose_tile_bf16(int32_t n, int32_t r, int num_cus, int32_t preci
   // gives every CU a workgroup of that size, then 64x64 direct-to-LDS rings,
   // then register-staged tiles as the fallback for small problems.
   static const int32_t pref_bf16j[] = {16, 18, 8, 7, 11, 10, 1, 2, 3};
-  static const int32_t pref_fp8j[] = {14, 9, 13, 1, 6, 2, 3};
+  static const int32_t pref_fp8j[] = {19, 14, 9, 13, 1, 6, 2, 3};
   static const int32_t pref_hilo[] = {18, 7, 10, 11, 1, 2, 3};
   static const int32_t pref_exact[] = {11, 8, 7, 1, 2, 3};
   const int32_t *order = pref_bf16j;
   int count = 9;
-  if (precision == SI_PREC_BF16X_FP8J) { order = pref_fp8j; count = 7; }
+  if (precision == SI_PREC_BF16X_FP8J) { order = pref_fp8j; count = 8; }
   if (precision == SI_PREC_BF16X_HILOJ) { order = pref_hilo; count = 7; }
   if (precision == SI_PREC_BF16X3_EXACTJ) { order = pref_exact; count = 6; }
   int32_t best = 1;
