@@ -159,11 +159,11 @@ si_status spring_ising_init(si_ctx **out, int32_t n, int32_t r, const float *J,
  *       initial momenta are 0.
  * Precisions: FP32 (64x64 tiles, instances padded to 64), or the BF16 forms
  * BF16X_FP8J (every J exact in FP8), BF16X_HILOJ and BF16X_MIXEDJ (FP8 J
- * where exact, hi + lo BF16 J otherwise), on 64x64 tiles with instances
+ * where exact, hi + lo BF16 J otherwise), on 128x64 tiles with instances
  * padded to 128; BF16X_BF16J and BF16X3_EXACTJ: SI_ERR_UNSUPPORTED.  Each
  * instance's trajectory equals the single-instance run of the same form on
- * the 64x64 tile of that shape (FP32: tile 14; FP8 J: BF16 tile 9; hi + lo:
- * BF16 tile 7) bit for bit.  In every later call the
+ * the 64x64 tile of that slab depth (FP32: tile 14; FP8 J: BF16 tile 9;
+ * hi + lo: BF16 tile 7) bit for bit.  In every later call the
  * instances are concatenated: state/spin arrays hold instance i's r*n[i]
  * values (replica-major) at offset r * (n[0] + ... + n[i-1]); energies hold
  * instance i's r values at offset r*i.  set_field and

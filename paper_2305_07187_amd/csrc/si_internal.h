@@ -109,8 +109,9 @@ struct BStepArgs {
 hipError_t launch_step_bf16(int32_t tile, int32_t precision, const BStepArgs &a, hipStream_t s);
 // Batched precision form: per-instance J format (fmt 1: FP8 e4m3, 2: hi + lo
 // BF16), BF16 plane of q per instance; instances padded to 128 (FP8 slabs
-// are 128 deep).  `base` carries the schedules, constants and r_pad.
-constexpr int BATCH_BF16_NPAD = 128;
+// are 128 deep), work items of 128 rows.  `base` carries the schedules,
+// constants and r_pad.
+constexpr int BATCH_BF16_NPAD = 128, BATCH_BF16_BM = 128;
 struct BBatchDesc {
   const void *Ja, *Jb;
   float *q[2], *p[2];

@@ -615,9 +615,9 @@ si_status spring_ising_init_batch(si_ctx **out, int32_t n_inst, const int32_t *n
   for (int32_t i = 0; i < n_inst; ++i) order[i] = i;
   std::stable_sort(order.begin(), order.end(),
                    [&](int32_t x, int32_t y) { return c->b_npad[x] > c->b_npad[y]; });
-  // (the BF16 tiles are 64 x 64 like the FP32 ones)
+  const int32_t item_rows = lowp ? BATCH_BF16_BM : BATCH_BM;
   for (int32_t i : order)
-    for (int32_t rt = 0; rt < c->b_npad[i] / BATCH_BM; ++rt)
+    for (int32_t rt = 0; rt < c->b_npad[i] / item_rows; ++rt)
       for (int32_t ct = 0; ct < c->r_pad / BATCH_BN; ++ct) c->b_items_host.push_back(int4{i, rt, ct, 0});
   BINIT_HIP(c->alloc(&c->b_desc, n_inst));
   BINIT_HIP(c->alloc(&c->b_items, (int64_t)c->b_items_host.size()));
@@ -1330,7 +1330,8 @@ si_status spring_ising_info(si_ctx *c, si_info *info) {
   info->resident_steps = info->resident_groups ? c->resident_min_steps : 0;
   if (c->n_inst)
     snprintf(info->kernel_name, sizeof info->kernel_name, "step_batch_%s_%dx%d_x%d",
-             c->b_lowp ? "bf16" : "f32", BATCH_BM, BATCH_BN, c->n_inst);
+             c->b_lowp ? "bf16" : "f32", c->b_lowp ? BATCH_BF16_BM : BATCH_BM, BATCH_BN,
+             c->n_inst);
   else if (split_for(c, c->tile) > 1)
     snprintf(info->kernel_name, sizeof info->kernel_name, "%s_ks%d",
              shape_of(c->prm.precision, c->tile).name, split_for(c, c->tile));

