@@ -313,6 +313,16 @@ def main():
                    "best_energy": float(e.min()), "mean_energy": float(e.mean())},
     }
 
+    if fp32_line and not args.no_forms:
+        # the same workload with the positions' wall at |q| = 1 instead of sqrt 2
+        m1 = si.SpringIsing(J, x0, total_steps=iters, precision="fp32", qmax=1.0)
+        m1.run(iters)
+        e1 = m1.energy(exact=bool(m1.info()["j_integer"])).cpu().numpy().astype(np.float64)
+        m1.close()
+        c1 = (W - e1) / 2
+        out["result_qmax1"] = {"best_cut": float(c1.max()), "mean_cut": float(c1.mean()),
+                               "best_energy": float(e1.min()), "mean_energy": float(e1.mean())}
+
     if fp32_line and not args.no_forms and iters % CHECK_EVERY == 0 and args.couplings == "pm1":
         from scipy.stats import ks_2samp
         target = float(np.sort(e)[max(0, int(0.01 * r) - 1)])  # 1% quantile (10th best)
