@@ -52,7 +52,7 @@ MEASURED_TRAFFIC_BYTES = {
     ("step_bf16_64x64_w2x2_k128_s3", "bf16x_fp8j", 2000, 1024): 75.60e6,
     ("step_bf16_64x64_w2x2_k64_s4", "bf16x_bf16j", 2000, 1024): 79.78e6,
     ("step_bf16_128x128_w4x2_k128_s3", "bf16x_fp8j", 2000, 2048): 146.94e6,
-    ("step_bf16_128x128_w2x4_k64_s3", "bf16x_hiloj", 8000, 2048): 1976.30e6,
+    ("step_bf16_128x256_w2x4_k64_s2", "bf16x_hiloj", 8000, 2048): 1143.96e6,
 }
 
 

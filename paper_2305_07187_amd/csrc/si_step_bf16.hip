@@ -227,12 +227,14 @@ struct Bf16DmaCfg {
   static constexpr int L = JP * A_DMA + QP * B_DMA;  // loads per wave per slab
   static constexpr int A_BYTES = BM * ROWA, B_BYTES = BN * ROWB;
   static constexpr int SLOT = JP * A_BYTES + QP * B_BYTES;
-  static constexpr int LDS_BYTES = STAGES * SLOT;
+  // the ring, or the update tile staged through the same LDS if larger
+  static constexpr int EPI_BYTES = BN * (BM + 4) * 4;
+  static constexpr int LDS_BYTES = STAGES * SLOT > EPI_BYTES ? STAGES * SLOT : EPI_BYTES;
   static_assert(CHA >= 8 && CHB >= 8, "rows of at least 128 bytes for the chunk swizzle");
   static_assert(A_DMA >= 1 && B_DMA >= 1 && BM % (RPDA * NW) == 0 && BN % (RPDB * NW) == 0,
                 "direct-to-LDS slab split");
   static_assert(TM >= 1 && TN >= 1 && BK % 32 == 0, "tile");
-  static_assert(STAGES >= 3 && (STAGES - 2) * L <= 63, "pipeline depth");
+  static_assert(STAGES >= 2 && (STAGES - 2) * L <= 63, "pipeline depth");
 };
 
 __device__ __forceinline__ uint32_t pack_hi16(float lo, float hi) {
@@ -570,8 +572,11 @@ static hipError_t launch_bd(const BStepArgs &a, hipStream_t s) {
 }
 
 // BF16 tile table: id, BM, BN, waves WM x WN, slab depth BK.
-// Stages 0: register-staged double buffer; >= 3: direct-to-LDS ring (the
-// FP8 J form needs BK = 128 there).
+// Stages 0: register-staged double buffer; >= 2: direct-to-LDS ring of that
+// many slabs (the FP8 J form needs BK = 128 there).  The two-slab rings
+// (20, 21) give eight waves 64x64 output blocks, which halves the LDS
+// fragment reads per matrix-core operation of the multi-plane forms (hi + lo
+// J, three position planes); one slab loads while the other is consumed.
 #define SI_BF16_TILES(X)         \
   X(1, 64, 64, 2, 2, 64, 0)      \
   X(2, 64, 128, 2, 2, 64, 0)     \
@@ -591,7 +596,9 @@ static hipError_t launch_bd(const BStepArgs &a, hipStream_t s) {
   X(16, 128, 256, 2, 4, 64, 3)   \
   X(17, 256, 128, 4, 2, 64, 3)   \
   X(18, 128, 128, 2, 4, 64, 3)   \
-  X(19, 128, 128, 4, 2, 128, 3)
+  X(19, 128, 128, 4, 2, 128, 3)  \
+  X(20, 128, 256, 2, 4, 64, 2)   \
+  X(21, 256, 128, 4, 2, 64, 2)
 
 TileShape tile_shape_bf16(int32_t tile) {
   switch (tile) {
