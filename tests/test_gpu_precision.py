@@ -165,6 +165,36 @@ def test_bf16_tiles_agree(precision, group):
             assert np.array_equal(cur[0], ref[0]) and np.array_equal(cur[1], ref[1]), name
 
 
+@pytest.mark.parametrize("precision,group", [
+    ("bf16x_bf16j", (16, 18, 20, 21)),
+    ("bf16x_hiloj", (18, 20, 21)),
+    ("bf16x3_exactj", (11, 21))])
+def test_large_bf16_tiles_agree_ragged(precision, group):
+    # The two-slab 128x256 / 256x128 rings against the three-slab rings on a
+    # ragged shape: the row and replica padding differ between the tiles
+    # (N = 300 pads to 384 or 512), and the extra zero slabs and columns
+    # must leave every value unchanged.
+    import torch
+    announce(f"{precision} large tiles agree on N=300 R=200 {group}")
+    n, r, S = 300, 200, 30
+    J = instances.make_gauss(n, 9) if precision == "bf16x_hiloj" else instances.make_pm1(n, 9)
+    x0 = instances.make_x0(n, r, 9)
+    ref = None
+    for tile in group:
+        m = _model(J, x0, S, precision, tile=tile)
+        assert m.info()["tile"] == tile
+        m.run(S)
+        x, p, _ = m.state()
+        torch.cuda.synchronize()
+        cur = (x.cpu().numpy(), p.cpu().numpy())
+        name = m.info()["kernel_name"]
+        m.close()
+        if ref is None:
+            ref = cur
+        else:
+            assert np.array_equal(cur[0], ref[0]) and np.array_equal(cur[1], ref[1]), name
+
+
 def _runs(precision, cases, S, steps):
     import torch
     res = []
