@@ -71,9 +71,8 @@ __device__ __forceinline__ void wait_vm_barrier() {
 }
 
 // Direct-to-LDS pipeline.  Each slab row of BK floats is stored unpadded;
-// its 16-byte chunk c sits at position c ^ (row & m), m = min(chunks per
-// row, 16) - 1, which spreads the 128-bit fragment reads of eight (128-byte
-// rows) or sixteen (longer rows) consecutive rows over distinct banks.  A
+// its 16-byte chunk c sits at position c ^ lds_swz(row), which spreads the
+// 128-bit fragment reads of consecutive rows over distinct banks.  A
 // direct-to-LDS load writes 16 bytes per lane at consecutive addresses, so
 // lane L fetches the global chunk that belongs at its destination.
 template <class C>
@@ -97,7 +96,6 @@ __device__ __forceinline__ void f32_mainloop_dma(const float *__restrict__ A,
   const int wy = wave / C::WN, wx = wave % C::WN;
   const int lrow = lane % C::MB, lk = (lane / C::MB) * 4;
   const int drow = lane / CH, dch = lane % CH;
-  constexpr int SW = (CH < 16 ? CH : 16) - 1;  // chunk swizzle mask
 
   typename C::acc_t part[C::TM][C::TN][C::KS];
 #pragma unroll
@@ -115,12 +113,12 @@ __device__ __forceinline__ void f32_mainloop_dma(const float *__restrict__ A,
 #pragma unroll
   for (int d = 0; d < A_DMA; ++d) {
     const int row = (wave * A_DMA + d) * RPD + drow;
-    srcA[d] = A + (size_t)(m0 + row) * ld + ((dch ^ (row & SW)) * 4);
+    srcA[d] = A + (size_t)(m0 + row) * ld + ((dch ^ lds_swz<CH>(row)) * 4);
   }
 #pragma unroll
   for (int d = 0; d < B_DMA; ++d) {
     const int row = (wave * B_DMA + d) * RPD + drow;
-    srcB[d] = B + (size_t)(n0 + row) * ld + ((dch ^ (row & SW)) * 4);
+    srcB[d] = B + (size_t)(n0 + row) * ld + ((dch ^ lds_swz<CH>(row)) * 4);
   }
   auto issue = [&](int kt, int slot) {
     float *st = smem + slot * SLAB;
@@ -162,12 +160,12 @@ __device__ __forceinline__ void f32_mainloop_dma(const float *__restrict__ A,
 #pragma unroll
       for (int i = 0; i < C::TM; ++i) {
         const int r = ra + i * C::MB;
-        fa[i] = *reinterpret_cast<const floatx4 *>(st + r * C::BK + ((ch ^ (r & SW)) << 2));
+        fa[i] = *reinterpret_cast<const floatx4 *>(st + r * C::BK + ((ch ^ lds_swz<CH>(r)) << 2));
       }
 #pragma unroll
       for (int j = 0; j < C::TN; ++j) {
         const int r = rb + j * C::MB;
-        fb[j] = *reinterpret_cast<const floatx4 *>(st + (C::BM + r) * C::BK + ((ch ^ (r & SW)) << 2));
+        fb[j] = *reinterpret_cast<const floatx4 *>(st + (C::BM + r) * C::BK + ((ch ^ lds_swz<CH>(r)) << 2));
       }
     };
     frag(0, a[0], b[0]);

@@ -27,6 +27,23 @@ __device__ __forceinline__ int xcd_tile(int b, int groups) {
   return (b % NUM_XCD) * per + b / NUM_XCD;
 }
 
+// Chunk swizzle of the direct-to-LDS slabs: the 16-byte chunk c of slab row
+// r (CH chunks per row) is stored at position c ^ lds_swz<CH>(r), so that
+// the 128-bit fragment reads of 16 consecutive rows (the lanes the LDS
+// serves together, over 64 banks) hit distinct banks.  Rows of 256 bytes or
+// more start on the same bank, so 16 distinct positions suffice.  Rows of
+// 128 bytes (CH = 8) pair up on the banks (rows r and r + 2 share them), so
+// the second half of each 16-row group uses the order of the first with
+// the lowest bit flipped; a plain eight-row order would meet itself there.
+template <int CH>
+__device__ __forceinline__ int lds_swz(int r) {
+  static_assert(CH == 8 || CH >= 16, "rows of 8 or more chunks");
+  if constexpr (CH == 8)
+    return (r ^ (r >> 3)) & 7;
+  else
+    return r & 15;
+}
+
 struct TileShape {
   int32_t bm, bn;
   const char *name;

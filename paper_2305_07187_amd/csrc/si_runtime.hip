@@ -292,7 +292,7 @@ static int32_t choose_tile_bf16(int32_t n, int32_t r, int num_cus, int32_t preci
 
 static int32_t choose_tile(int32_t n, int32_t r, int num_cus) {
   // Preference from tile sweeps on MI355X: at N=2000, R=1024 the 8-wave
-  // direct-to-LDS tiles (128x64, then 64x128) lead; a problem with at least four
+  // direct-to-LDS tiles (64x128, then 128x64) lead; a problem with at least four
   // 64x128 tiles per CU and at least 128 replicas (N=8000, R=2048) runs best
   // on the register-staged 64x128 tile.
   {
@@ -301,7 +301,7 @@ static int32_t choose_tile(int32_t n, int32_t r, int num_cus) {
         (round_up(n, big.bm) / big.bm) * (round_up(r, big.bn) / big.bn) >= 4 * (int64_t)num_cus)
       return 1;
   }
-  const int32_t order[] = {26, 27, 2, 9, 12, 6, 3};
+  const int32_t order[] = {27, 26, 2, 9, 12, 6, 3};
   int32_t best = 3;
   int64_t best_tiles = -1;
   for (int32_t t : order) {

@@ -221,8 +221,6 @@ struct Bf16DmaCfg {
   static constexpr int ROWA = BK * EA, ROWB = BK * 2;  // bytes per row
   static constexpr int CHA = ROWA / 16, CHB = ROWB / 16;
   static constexpr int RPDA = 64 / CHA, RPDB = 64 / CHB;  // rows per wave-wide load
-  static constexpr int SWA = (CHA < 16 ? CHA : 16) - 1;    // chunk swizzle masks
-  static constexpr int SWB = (CHB < 16 ? CHB : 16) - 1;
   static constexpr int A_DMA = BM / RPDA / NW, B_DMA = BN / RPDB / NW;
   static constexpr int L = JP * A_DMA + QP * B_DMA;  // loads per wave per slab
   static constexpr int A_BYTES = BM * ROWA, B_BYTES = BN * ROWB;
@@ -284,7 +282,7 @@ __device__ __forceinline__ void bf16_mainloop_dma(const BStepArgs &a, int m0, in
 #pragma unroll
       for (int d = 0; d < C::A_DMA; ++d) {
         const int row = (wave * C::A_DMA + d) * C::RPDA + drow;
-        srcA[pl][d] = base + ((size_t)(m0 + row) * ld) * C::EA + (dch ^ (row & C::SWA)) * 16;
+        srcA[pl][d] = base + ((size_t)(m0 + row) * ld) * C::EA + (dch ^ lds_swz<C::CHA>(row)) * 16;
       }
     }
   }
@@ -297,7 +295,7 @@ __device__ __forceinline__ void bf16_mainloop_dma(const BStepArgs &a, int m0, in
 #pragma unroll
       for (int d = 0; d < C::B_DMA; ++d) {
         const int row = (wave * C::B_DMA + d) * C::RPDB + drow;
-        srcB[pl][d] = base + ((size_t)(n0 + row) * ld) * 2 + (dch ^ (row & C::SWB)) * 16;
+        srcB[pl][d] = base + ((size_t)(n0 + row) * ld) * 2 + (dch ^ lds_swz<C::CHB>(row)) * 16;
       }
     }
   }
@@ -347,7 +345,7 @@ __device__ __forceinline__ void bf16_mainloop_dma(const BStepArgs &a, int m0, in
         if (C::JFMT == 1) {
           const int ch = (kk + 16 * h) / 16;  // 16 fp8 per chunk
           const uintx4 w = *reinterpret_cast<const uintx4 *>(st + r * C::ROWA +
-                                                             ((ch ^ (r & C::SWA)) << 4));
+                                                             ((ch ^ lds_swz<C::CHA>(r)) << 4));
           fa[0][i][0] = fp8x8_to_bf16x8(w[0], w[1]);
           fa[0][i][1] = fp8x8_to_bf16x8(w[2], w[3]);
         } else {
@@ -357,7 +355,7 @@ __device__ __forceinline__ void bf16_mainloop_dma(const BStepArgs &a, int m0, in
             for (int sidx = 0; sidx < 2; ++sidx) {
               const int ch = (kk + 16 * h + 8 * sidx) / 8;  // 8 bf16 per chunk
               fa[pl][i][sidx] = *reinterpret_cast<const bf16x8 *>(
-                  st + pl * C::A_BYTES + r * C::ROWA + ((ch ^ (r & C::SWA)) << 4));
+                  st + pl * C::A_BYTES + r * C::ROWA + ((ch ^ lds_swz<C::CHA>(r)) << 4));
             }
         }
       }
@@ -370,7 +368,7 @@ __device__ __forceinline__ void bf16_mainloop_dma(const BStepArgs &a, int m0, in
           for (int sidx = 0; sidx < 2; ++sidx) {
             const int ch = (kk + 16 * h + 8 * sidx) / 8;
             fb[pl][j][sidx] = *reinterpret_cast<const bf16x8 *>(
-                st + C::JP * C::A_BYTES + pl * C::B_BYTES + r * C::ROWB + ((ch ^ (r & C::SWB)) << 4));
+                st + C::JP * C::A_BYTES + pl * C::B_BYTES + r * C::ROWB + ((ch ^ lds_swz<C::CHB>(r)) << 4));
           }
       }
 #pragma unroll
