@@ -235,22 +235,14 @@ struct Bf16DmaCfg {
   static_assert(STAGES >= 2 && (STAGES - 2) * L <= 63, "pipeline depth");
 };
 
-__device__ __forceinline__ uint32_t pack_hi16(float lo, float hi) {
-  return (__float_as_uint(hi) & 0xFFFF0000u) | (__float_as_uint(lo) >> 16);
-}
-
-// 8 FP8 e4m3 values (two words) -> 8 BF16 (exact: e4m3 has 4 significant bits)
+// 8 FP8 e4m3 values (two words) -> 8 BF16 (exact: e4m3 has 4 significant
+// bits), two values per conversion instruction at unit scale.
 __device__ __forceinline__ bf16x8 fp8x8_to_bf16x8(uint32_t w0, uint32_t w1) {
-  typedef float floatx2 __attribute__((ext_vector_type(2)));
-  const floatx2 a = __builtin_amdgcn_cvt_pk_f32_fp8((int)w0, false);
-  const floatx2 b = __builtin_amdgcn_cvt_pk_f32_fp8((int)w0, true);
-  const floatx2 c = __builtin_amdgcn_cvt_pk_f32_fp8((int)w1, false);
-  const floatx2 d = __builtin_amdgcn_cvt_pk_f32_fp8((int)w1, true);
   uintx4 u;
-  u[0] = pack_hi16(a[0], a[1]);
-  u[1] = pack_hi16(b[0], b[1]);
-  u[2] = pack_hi16(c[0], c[1]);
-  u[3] = pack_hi16(d[0], d[1]);
+  u[0] = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(w0, 1.0f, false));
+  u[1] = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(w0, 1.0f, true));
+  u[2] = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(w1, 1.0f, false));
+  u[3] = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(w1, 1.0f, true));
   return __builtin_bit_cast(bf16x8, u);
 }
 
