@@ -292,13 +292,16 @@ static int32_t choose_tile_bf16(int32_t n, int32_t r, int num_cus, int32_t preci
 
 static int32_t choose_tile(int32_t n, int32_t r, int num_cus) {
   // Preference from tile sweeps on MI355X: at N=2000, R=1024 the 8-wave
-  // direct-to-LDS tiles (64x128, then 128x64) lead; a problem with at least four
-  // 64x128 tiles per CU and at least 128 replicas (N=8000, R=2048) runs best
-  // on the register-staged 64x128 tile.
+  // direct-to-LDS tiles (64x128, then 128x64) lead; a problem with at least
+  // two 64x128 tiles per CU and at least 128 replicas (N=2000 with R=2048,
+  // N=4000 with R=1024, N=8000) runs best on the register-staged 64x128
+  // tile, two of whose four-wave workgroups share a CU and keep its matrix
+  // cores busy through each other's barriers.  Rows are counted as init
+  // pads them (to a multiple of 128).
   {
     const TileShape big = tile_shape(1);
     if (r >= big.bn &&
-        (round_up(n, big.bm) / big.bm) * (round_up(r, big.bn) / big.bn) >= 4 * (int64_t)num_cus)
+        (round_up(n, 128) / big.bm) * (round_up(r, big.bn) / big.bn) >= 2 * (int64_t)num_cus)
       return 1;
   }
   const int32_t order[] = {27, 26, 2, 9, 12, 6, 3};
