@@ -191,11 +191,10 @@ __device__ __forceinline__ void bf16_mainloop(const BStepArgs &a, int m0, int n0
 // Direct-to-LDS pipeline for the BF16 forms.  STAGES slots of LDS hold the
 // J plane(s) and the q plane(s) of one slab each; STAGES - 1 slabs are in
 // flight.  Rows are stored unpadded with the 16-byte chunk c of row r at
-// position c ^ (r & m), m = min(chunks per row, 16) - 1 (rows of 128 or 256
-// bytes), which keeps the 128-bit
-// fragment reads of eight consecutive rows on distinct banks.  FP8 J stays
-// one byte per coupling in LDS and is widened to BF16 by the hardware FP8
-// conversion when the fragment is read.
+// position c ^ lds_swz(r) (rows of 128 or 256 bytes), which keeps the
+// 128-bit fragment reads of 16 consecutive rows on distinct banks.  FP8 J
+// stays one byte per coupling in LDS and is widened to BF16 by the hardware
+// FP8 conversion when the fragment is read.
 //
 // Contraction slots: the MFMAs run in pairs over 32 indices; in MFMA s of a
 // pair, lane half h = l/32 holds indices kk + 16h + 8s .. +7.
