@@ -30,4 +30,4 @@ from .spring_ising import (  # noqa: F401
     dt_schedule,
 )
 from .bruteforce import ground_state_bruteforce  # noqa: F401
-from .adjoint import relaxed_energy_grad  # noqa: F401
+from .adjoint import relaxed_energy_grad, relaxed_energy_grad_along  # noqa: F401

@@ -37,7 +37,6 @@ def relaxed_energy_grad(J, Q0, P0, dt, zeta, k=PAPER["k"], m=PAPER["m"],
     dt = np.asarray(dt, dtype=np.float64)
     zeta = np.asarray(zeta, dtype=np.float64)
     S = len(dt)
-    R = Q.shape[1]
     qs, ps, umask, vmask = [], [], [], []
     for n in range(S):
         U = Q + (dt[n] / m) * P
@@ -48,6 +47,41 @@ def relaxed_energy_grad(J, Q0, P0, dt, zeta, k=PAPER["k"], m=PAPER["m"],
         vmask.append(np.abs(V) <= pmax)
         Q = np.clip(U, -qmax, qmax)
         P = np.clip(V, -pmax, pmax)
+    return _reverse_sweep(J, qs, ps, umask, vmask, Q, dt, zeta, k, m)
+
+
+def relaxed_energy_grad_along(J, Qs, Ps, dt, zeta, k=PAPER["k"], m=PAPER["m"],
+                              qmax=PAPER["qmax"], pmax=PAPER["pmax"]):
+    """The same gradient along a given trajectory: Qs[n], Ps[n] are the
+    states after n steps (n = 0 .. S, [N, R] each), for instance those of
+    another implementation of the forward map.  The wall masks of every
+    step are evaluated from those states; the reverse sweep is the one of
+    relaxed_energy_grad.  Returns (L, dL/ddt [S], dL/dzeta [S])."""
+    J = np.asarray(J, dtype=np.float64)
+    dt = np.asarray(dt, dtype=np.float64)
+    zeta = np.asarray(zeta, dtype=np.float64)
+    S = len(dt)
+    if len(Qs) != S + 1 or len(Ps) != S + 1:
+        raise ValueError("need the S + 1 states q_0 .. q_S and p_0 .. p_S")
+    qs, ps, umask, vmask = [], [], [], []
+    for n in range(S):
+        Q = np.asarray(Qs[n], dtype=np.float64)
+        P = np.asarray(Ps[n], dtype=np.float64)
+        U = Q + (dt[n] / m) * P
+        V = P + dt[n] * (-k * Q + zeta[n] * (J @ Q))
+        qs.append(Q)
+        ps.append(P)
+        umask.append(np.abs(U) <= qmax)
+        vmask.append(np.abs(V) <= pmax)
+    return _reverse_sweep(J, qs, ps, umask, vmask, np.asarray(Qs[S], dtype=np.float64), dt,
+                          zeta, k, m)
+
+
+def _reverse_sweep(J, qs, ps, umask, vmask, Q, dt, zeta, k, m):
+    """Loss at the final positions Q and the reverse sweep over the stored
+    states and wall masks (the recurrences in the module docstring)."""
+    S = len(dt)
+    R = Q.shape[1]
     JQ = J @ Q
     loss = float((-0.5 * np.einsum("ir,ir->r", Q, JQ)).mean())
     lam_q = -(1.0 / R) * JQ

@@ -109,6 +109,42 @@ def test_adjoint_full_size_first_steps():
     assert _rel(gd, gdo) <= 1e-3 and _rel(gz, gzo) <= 1e-3
 
 
+def test_adjoint_full_configuration_along_gpu_trajectory():
+    # The whole differentiation workload (N=2000, R=64, 2000 steps,
+    # checkpoints every 100).  Over 2000 steps the FP32 and FP64 forward
+    # trajectories part ways, so the oracle's reverse sweep runs along the
+    # GPU's own forward states (recorded step by step; the GPU's adjoint
+    # recomputes exactly these from its checkpoints): what remains to
+    # compare is the backward arithmetic and the wall masks.
+    import torch
+    n, r, S = 2000, 64, 2000
+    announce(f"adjoint full configuration N={n} R={r} S={S} along the GPU trajectory")
+    si = ensure_built()
+    J = instances.make_pm1(n, 0)
+    x0 = instances.make_x0(n, r, 0)
+    dt, zeta = _sched(S, S)
+    m = si.SpringIsing(to_dev(J), to_dev(x0), total_steps=S)
+    Qs, Ps = [x0.T], [np.zeros((n, r), np.float32)]
+    for _ in range(S):
+        m.step()
+        x, p, _ = m.state()
+        torch.cuda.synchronize()
+        Qs.append(x.cpu().numpy().T)
+        Ps.append(p.cpu().numpy().T)
+    m.set_state(to_dev(x0), None, 0)
+    loss, gd, gz = m.relaxed_energy_grad(100)
+    torch.cuda.synchronize()
+    L, gd, gz = float(loss.cpu()[0]), gd.cpu().numpy(), gz.cpu().numpy()
+    m.close()
+    Lo, gdo, gzo = oracle.relaxed_energy_grad_along(J.astype(np.float64), Qs, Ps,
+                                                    dt.astype(np.float64),
+                                                    zeta.astype(np.float64), qmax=QMAX)
+    announce(f"  loss {L:.8e} vs {Lo:.8e}; grad rel err dt {_rel(gd, gdo):.2e} "
+             f"zeta {_rel(gz, gzo):.2e}")
+    assert abs(L - Lo) <= 1e-5 * abs(Lo)
+    assert _rel(gd, gdo) <= 1e-3 and _rel(gz, gzo) <= 1e-3
+
+
 def test_adjoint_vs_device_finite_differences():
     # At the differentiation workload's shape (N=2000, R=64), in the smooth
     # regime (zeta * lambda_max < k, walls never reached): the adjoint's

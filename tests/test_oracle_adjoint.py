@@ -46,6 +46,34 @@ def test_adjoint_matches_autograd_replay(n, r, S, m):
                                                                    qmax=F32_SQRT2)["Q"]), rel=1e-12)
 
 
+def test_adjoint_along_a_given_trajectory():
+    # The gradient along an externally supplied trajectory (here the
+    # states of the independent torch forward) equals torch autograd's
+    # gradient of that same forward.
+    n, r, S = 20, 4, 90
+    J = instances.make_pm1(n, 6).astype(np.float64)
+    Q0 = instances.make_x0(n, r, 3).T.astype(np.float64)
+    dt = oracle.dt_schedule(S).astype(np.float64)
+    zeta = oracle.zeta_schedule(S).astype(np.float64)
+    Jt = torch.tensor(J, dtype=torch.float64)
+    q = torch.tensor(Q0, dtype=torch.float64)
+    p = torch.zeros_like(q)
+    Qs, Ps = [q.numpy().copy()], [p.numpy().copy()]
+    for k in range(S):
+        u = q + float(dt[k]) * p
+        v = p + float(dt[k]) * (-0.5 * q + float(zeta[k]) * (Jt @ q))
+        q, p = torch.clamp(u, -F32_SQRT2, F32_SQRT2), torch.clamp(v, -2.0, 2.0)
+        Qs.append(q.numpy().copy())
+        Ps.append(p.numpy().copy())
+    L, gd, gz = oracle.relaxed_energy_grad_along(J, Qs, Ps, dt, zeta, qmax=F32_SQRT2)
+    Lt, gdt, gzt = _torch_replay(J, Q0, dt, zeta)
+    assert L == pytest.approx(Lt, rel=1e-12)
+    np.testing.assert_allclose(gd, gdt, rtol=1e-9, atol=1e-9 * np.abs(gdt).max())
+    np.testing.assert_allclose(gz, gzt, rtol=1e-9, atol=1e-9 * np.abs(gzt).max())
+    with pytest.raises(ValueError):
+        oracle.relaxed_energy_grad_along(J, Qs[:-1], Ps[:-1], dt, zeta)
+
+
 def test_adjoint_central_differences():
     # Smooth regime (walls not reached): central FD along random directions.
     n, r, S = 12, 4, 30
