@@ -53,6 +53,34 @@ def test_exact_split_meets_fp32_bar():
     announce(f"  final energies {e.tolist()} oracle {e_ref.tolist()}")
 
 
+@pytest.mark.parametrize("precision", ["bf16x_bf16j", "bf16x_fp8j", "bf16x_hiloj"])
+def test_single_plane_forms_divergence_reported(precision):
+    # The one-plane forms round q to BF16 in every product, so they leave
+    # the FP64 trajectory at once; the normwise divergence over the first
+    # 100 steps is reported (the per-step error is bounded by the one-step
+    # tests).  Sanity bar: it stays below 1 in max-norm relative terms
+    # and grows from the BF16 unit roundoff, not from a wrong step.
+    import torch
+    n, r, S = 100, 8, 1000
+    announce(f"{precision} trajectory divergence N={n} R={r}, 100 steps")
+    J = instances.make_gauss(n, 0) if precision == "bf16x_hiloj" else instances.make_pm1(n, 0)
+    x0 = instances.make_x0(n, r, 0)
+    m = _model(J, x0, S, precision)
+    dt, zeta = oracle_schedules(S)
+    ref = oracle.run(J.astype(np.float64), x0.T.astype(np.float64), None, dt, zeta, qmax=QMAX,
+                     n_steps=100, record=range(101))
+    report = {}
+    for k in range(1, 101):
+        m.step()
+        if k in (1, 10, 25, 50, 100):
+            x, p, _ = m.state()
+            torch.cuda.synchronize()
+            report[k] = (rel_err(x.cpu().numpy(), ref["traj"][k][0]),
+                         rel_err(p.cpu().numpy(), ref["traj"][k][1]))
+    announce("  " + ", ".join(f"step {k}: q {a:.2e} p {b:.2e}" for k, (a, b) in report.items()))
+    assert report[1][1] <= 2.0 ** -7 and all(a < 1.0 and b < 1.0 for a, b in report.values())
+
+
 def test_exact_split_full_size_sampled():
     import torch
     n, r, S = 2000, 1024, 5000
