@@ -135,13 +135,17 @@ __global__ __launch_bounds__(ACfg::NT) void adj_step_kernel(
   }
 }
 
+// One workgroup per step: workgroup b reduces the nwg partial triples of
+// step n0 + b, stored at part + b * nwg * 3, in a fixed order.
 __global__ __launch_bounds__(256) void adj_reduce_kernel(const double *__restrict__ part, int nwg,
                                                          int mode, double *loss, double *g_dt,
                                                          double *g_zeta, const float *dts,
-                                                         const float *zetas, int n, float k,
+                                                         const float *zetas, int n0, float k,
                                                          float inv_m, int r_count) {
   __shared__ double red[3][256];
   const int t = threadIdx.x;
+  const int n = n0 + (int)blockIdx.x;
+  part += (size_t)blockIdx.x * nwg * 3;
   double s[3] = {0.0, 0.0, 0.0};
   for (int w = t; w < nwg; w += 256)
 #pragma unroll
@@ -194,9 +198,11 @@ hipError_t launch_adj_step(const float *J, const float *lamq_in, const float *la
 
 hipError_t launch_adj_reduce(const double *part, int32_t nwg, int32_t mode, double *loss,
                              double *g_dt, double *g_zeta, const float *dt, const float *zeta,
-                             int32_t n, float k, float inv_m, int32_t r_count, hipStream_t s) {
-  adj_reduce_kernel<<<1, 256, 0, s>>>(part, nwg, mode, loss, g_dt, g_zeta, dt, zeta, n, k, inv_m,
-                                      r_count);
+                             int32_t n, int32_t n_steps, float k, float inv_m, int32_t r_count,
+                             hipStream_t s) {
+  if (n_steps < 1 || (mode == 0 && n_steps != 1)) return hipErrorInvalidValue;
+  adj_reduce_kernel<<<n_steps, 256, 0, s>>>(part, nwg, mode, loss, g_dt, g_zeta, dt, zeta, n, k,
+                                            inv_m, r_count);
   return hipGetLastError();
 }
 

@@ -189,11 +189,13 @@ hipError_t launch_adj_step_split(const float *J, const float *lamq_in, const flo
                                  const float *zeta, int32_t n, float k, float inv_m, int32_t n_pad,
                                  int32_t n_spins, int32_t r_pad, int32_t ksplit, float *W,
                                  hipStream_t s);
-// mode 0: loss[0] = -1/2 * sum(part[:,0]) / r_count;  mode 1: gradient entries
-// g_dt[n], g_zeta[n] from the three partial sums of step n.
+// mode 0 (n_steps = 1): loss[0] = -1/2 * sum(part[:,0]) / r_count;  mode 1:
+// gradient entries g_dt[n + i], g_zeta[n + i] for i < n_steps from the nwg
+// partial triples of step n + i at part + i * nwg * 3.
 hipError_t launch_adj_reduce(const double *part, int32_t nwg, int32_t mode, double *loss,
                              double *g_dt, double *g_zeta, const float *dt, const float *zeta,
-                             int32_t n, float k, float inv_m, int32_t r_count, hipStream_t s);
+                             int32_t n, int32_t n_steps, float k, float inv_m, int32_t r_count,
+                             hipStream_t s);
 
 // Layout conversion and validation.
 hipError_t launch_pack_matrix(const float *src, int32_t n, float *dst, int8_t *dst8,

@@ -141,6 +141,7 @@ struct si_ctx {
   float *adj_ckpt = nullptr, *adj_seg = nullptr, *adj_lam = nullptr;
   uint8_t *adj_mask = nullptr;
   double *adj_part = nullptr;
+  int64_t adj_part_cap = 0;       // doubles
   int64_t adj_ckpt_cap = 0, adj_seg_cap = 0;
 
   template <class T>
@@ -844,10 +845,13 @@ si_status spring_ising_relaxed_energy_grad(si_ctx *c, int32_t ckpt_every, double
     SI_HIP(c, c->alloc(&c->adj_mask, (int64_t)C * NR));
     c->adj_seg_cap = (int64_t)(C + 1) * 2 * NR;
   }
-  if (!c->adj_lam) {
-    SI_HIP(c, c->alloc(&c->adj_lam, 4 * NR));
-    const int32_t groups = nwg > nwg_seed ? nwg : nwg_seed;
-    SI_HIP(c, c->alloc(&c->adj_part, (int64_t)(groups > 1024 ? groups : 1024) * 3));
+  if (!c->adj_lam) SI_HIP(c, c->alloc(&c->adj_lam, 4 * NR));
+  // partial triples of every step of the sweep, reduced in one launch at the
+  // end (the seed's triples use the start of the same buffer first)
+  const int64_t part_need = (int64_t)(S - t0 > 1 ? S - t0 : 1) * (nwg > nwg_seed ? nwg : nwg_seed) * 3;
+  if (part_need > c->adj_part_cap) {
+    SI_HIP(c, c->alloc(&c->adj_part, part_need));
+    c->adj_part_cap = part_need;
   }
   const float inv_r = 1.0f / (float)c->r, inv_m = 1.0f / c->prm.m, k = c->prm.k;
   SI_HIP(c, launch_fill_f64(g_dt, S, 0.0, c->stream));
@@ -870,7 +874,7 @@ si_status spring_ising_relaxed_energy_grad(si_ctx *c, int32_t ckpt_every, double
   SI_HIP(c, launch_adj_seed(c->J, c->q[c->cur], lam[0][0], lam[0][1], c->adj_part, c->n_pad,
                             c->r_pad, inv_r, c->stream));
   SI_HIP(c, launch_adj_reduce(c->adj_part, nwg_seed, 0, loss, nullptr, nullptr, c->dt, c->zeta, 0,
-                              k, inv_m, c->r, c->stream));
+                              1, k, inv_m, c->r, c->stream));
   // reverse sweep, one segment at a time
   StepArgs a = step_args(c);
   for (int32_t sg = nseg - 1; sg >= 0; --sg) {
@@ -891,21 +895,24 @@ si_status spring_ising_relaxed_energy_grad(si_ctx *c, int32_t ckpt_every, double
     }
     for (int32_t j = len - 1; j >= 0; --j) {
       const int32_t n = t_a + j;
+      double *part = c->adj_part + (int64_t)(n - t0) * nwg * 3;
       if (asplit > 1)
         SI_HIP(c, launch_adj_step_split(c->J, lam[lc][0], lam[lc][1], c->adj_mask + (int64_t)j * NR,
                                         sq + 2 * j * NR, sq + 2 * j * NR + NR, lam[lc ^ 1][0],
-                                        lam[lc ^ 1][1], c->adj_part, c->dt, c->zeta, n, k, inv_m,
+                                        lam[lc ^ 1][1], part, c->dt, c->zeta, n, k, inv_m,
                                         c->n_pad, c->n, c->r_pad, asplit, c->fsplit, c->stream));
       else
         SI_HIP(c, launch_adj_step(c->J, lam[lc][0], lam[lc][1], c->adj_mask + (int64_t)j * NR,
                                   sq + 2 * j * NR, sq + 2 * j * NR + NR, lam[lc ^ 1][0],
-                                  lam[lc ^ 1][1], c->adj_part, c->dt, c->zeta, n, k, inv_m,
+                                  lam[lc ^ 1][1], part, c->dt, c->zeta, n, k, inv_m,
                                   c->n_pad, c->r_pad, c->stream));
-      SI_HIP(c, launch_adj_reduce(c->adj_part, nwg, 1, nullptr, g_dt, g_zeta, c->dt, c->zeta, n,
-                                  k, inv_m, c->r, c->stream));
       lc ^= 1;
     }
   }
+  // every step's gradient entries from its partial triples, in one launch
+  if (S > t0)
+    SI_HIP(c, launch_adj_reduce(c->adj_part, nwg, 1, nullptr, g_dt, g_zeta, c->dt, c->zeta, t0,
+                                S - t0, k, inv_m, c->r, c->stream));
   return SI_OK;
 }
 

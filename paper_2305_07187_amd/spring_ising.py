@@ -110,6 +110,10 @@ def load_library(path: str = LIB_PATH):
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is missing: build it with "
                            "`python -m paper_2305_07187_amd.build` (no fallback exists)")
+    # torch carries its own copy of the HIP runtime; load it first so that
+    # the library binds to that copy and recognises torch's device pointers
+    # (a second runtime in the process would not know them)
+    import torch  # noqa: F401
     lib = ctypes.CDLL(path)
     for name, args in _SIGNATURES.items():
         fn = getattr(lib, name)

@@ -92,3 +92,27 @@ def test_autotune_keeps_state_and_parity(precision):
                          qmax=QMAX, n_steps=50)
         assert rel_err(x.cpu().numpy(), ref["Q"]) <= 1e-5
     m.close()
+
+
+def test_library_loaded_before_torch():
+    # A fresh process that loads the library before it imports torch itself
+    # (torch ships its own HIP runtime; the binding loads it first so that
+    # torch's device pointers are recognised).
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = (
+        "import sys; sys.path.insert(0, %r)\n"
+        "from paper_2305_07187_amd import spring_ising as si\n"
+        "si.load_library()\n"
+        "import numpy as np, torch\n"
+        "from paper_2305_07187_amd import instances\n"
+        "J = torch.from_numpy(instances.make_pm1(64, 0)).cuda()\n"
+        "x = torch.from_numpy(instances.make_x0(64, 4, 0)).cuda()\n"
+        "m = si.SpringIsing(J, x, total_steps=10)\n"
+        "m.run(10); print('ok', m.energy().cpu().numpy().tolist())\n" % root)
+    announce("library loaded before torch, fresh process")
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=180)
+    assert r.returncode == 0 and "ok" in r.stdout, r.stdout[-500:] + r.stderr[-2000:]
+
