@@ -119,3 +119,14 @@ def test_null_context_calls():
                      ("spring_ising_set_field", [None])]:
         assert getattr(lib, fn)(None, *args) == si.SI_ERR_INVALID, fn
         assert "null context" in si.last_error()
+
+
+def test_c_program_builds(tmp_path):
+    # A C99 program built against include/ and the library alone (the GPU
+    # tests run it).
+    from c_demo import build_c_demo
+    ok, msg = build_c_demo(tmp_path / "c_abi_demo")
+    if not ok and "missing" in msg:
+        pytest.skip(msg)
+    assert ok, msg
+

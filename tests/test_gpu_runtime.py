@@ -116,3 +116,18 @@ def test_library_loaded_before_torch():
     r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=180)
     assert r.returncode == 0 and "ok" in r.stdout, r.stdout[-500:] + r.stderr[-2000:]
 
+
+def test_c_program_runs(tmp_path):
+    # The C ABI without Python or torch: tests/c_abi_demo.c allocates with
+    # the HIP runtime, steps a +-1 instance and checks the exact energies of
+    # the spins it reads back against Eq. (1) on the host.
+    import subprocess
+    from c_demo import build_c_demo
+    exe = tmp_path / "c_abi_demo"
+    ok, msg = build_c_demo(exe)
+    assert ok, msg
+    announce("C program through the C ABI")
+    r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=120)
+    announce("  " + r.stdout.strip())
+    assert r.returncode == 0 and "match" in r.stdout, r.stdout + r.stderr
+
