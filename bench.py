@@ -114,6 +114,7 @@ def batched_form(si, steps=300, n_inst=256, r=64, sequential=True):
         b.close()
     if not sequential:
         return out
+    out["time_to_target"] = batched_time_to_target(si, Js, xs)
     seq = 0.0
     for J, x in zip(Js, xs):
         m = si.SpringIsing(J, x, total_steps=30)
@@ -128,6 +129,48 @@ def batched_form(si, steps=300, n_inst=256, r=64, sequential=True):
     out["batched_vs_sequential_fp32"] = seq * 1000.0 / out["fp32_batched_ms_per_step"]
     out["bf16_vs_fp32_batched"] = (out["fp32_batched_ms_per_step"] /
                                    out["bf16x_mixedj_batched_ms_per_step"])
+    return out
+
+
+def batched_time_to_target(si, Js, xs, steps=3000, every=100, rank=7):
+    """Time to target energy of the batched forms over the batched workload's
+    3000 steps.  Each instance's target is the `rank`-th best of its R final
+    energies in the FP32 batch; a form's time to target is the HIP-event time
+    of the first check (every `every` steps, energies of all instances on the
+    stream) at which every instance has a replica at or below its target."""
+    import numpy as np
+    import torch
+
+    stream = torch.cuda.current_stream()
+    checks = steps // every
+    out = {"steps": steps, "check_every": every,
+           "target": f"per instance, the {rank}th best of R final FP32 energies"}
+    recorded = {}
+    for form in ("fp32", "bf16x_mixedj"):
+        b = si.SpringIsingBatch(Js, xs, total_steps=steps, precision=form)
+        b.run(every)  # warm-up
+        b.set_state(xs, None, 0)
+        torch.cuda.synchronize()
+        evs = [torch.cuda.Event(enable_timing=True) for _ in range(checks + 1)]
+        energies = []
+        evs[0].record(stream)
+        for c in range(checks):
+            b.run(every)
+            energies.append(b.energy(exact=False))
+            evs[c + 1].record(stream)
+        torch.cuda.synchronize()
+        times = [evs[0].elapsed_time(e) / 1000.0 for e in evs[1:]]
+        mins = np.stack([torch.stack(es).min(dim=1).values.cpu().numpy() for es in energies])
+        recorded[form] = (mins, times, torch.stack(energies[-1]).cpu().numpy())  # [instances, R]
+        b.close()
+    targets = np.sort(recorded["fp32"][2], axis=1)[:, rank - 1]
+    for form, (mins, times, _) in recorded.items():
+        hit = np.nonzero((mins <= targets[None, :]).all(axis=1))[0]
+        out[form] = {"ttt_s": float(times[hit[0]]) if len(hit) else None,
+                     "ttt_step": int((hit[0] + 1) * every) if len(hit) else None,
+                     "instances_at_target_at_end": int((mins[-1] <= targets).sum())}
+    t32, t16 = out["fp32"]["ttt_s"], out["bf16x_mixedj"]["ttt_s"]
+    out["bf16_speedup_vs_fp32"] = (t32 / t16) if (t32 and t16) else None
     return out
 
 

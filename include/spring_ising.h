@@ -244,7 +244,9 @@ si_status spring_ising_spins(si_ctx *ctx, int8_t *s);
  *   e_int : device, r int32, or NULL.  Exact; needs integer J (|J_ij| <= 127)
  *           and an integer field, else SI_ERR_UNSUPPORTED.
  *   e_real: device, r doubles, or NULL.  For integer J it equals e_int; for
- *           real J it is an FP32 product with a compensated FP32 sum. */
+ *           real J it is an FP32 product with a compensated FP32 sum.
+ * On a batch every instance is computed in two grouped launches (integer
+ * instances, then real ones), with the values of its single-instance call. */
 si_status spring_ising_energy(si_ctx *ctx, int32_t *e_int, double *e_real);
 
 /* In-run best state: evaluate the energy of the current spins (exactly for

@@ -23,15 +23,17 @@ constexpr int EBM = 64, EBN = 64, EBK = 64, ELDK = EBK + 16;  // bytes
 constexpr int EWTM = 32, EWTN = 32;  // 2 x 2 waves
 }  // namespace
 
-__global__ __launch_bounds__(256) void energy_i8_kernel(const int8_t *__restrict__ J8,
-                                                        const int8_t *__restrict__ S8,
-                                                        const int8_t *__restrict__ h8,
-                                                        int32_t *__restrict__ acc_out, int ld) {
+// One 64 x 64 output tile (rows m0.., replicas n0..) of G = J.S, reduced
+// against s (and h) into acc_out[col] by integer atomics.
+__device__ __forceinline__ void energy_i8_tile(const int8_t *__restrict__ J8,
+                                               const int8_t *__restrict__ S8,
+                                               const int8_t *__restrict__ h8,
+                                               int32_t *__restrict__ acc_out, int ld, int m0,
+                                               int n0) {
   __shared__ __attribute__((aligned(16))) int8_t As[2][EBM * ELDK];
   __shared__ __attribute__((aligned(16))) int8_t Bs[2][EBN * ELDK];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wy = wave >> 1, wx = wave & 1;
-  const int m0 = blockIdx.x * EBM, n0 = blockIdx.y * EBN;
   const int lrow = lane & 15, lk = (lane >> 4) * 16;
   // staging: each thread moves 16 bytes of A and 16 bytes of B per slab
   const int srow = tid >> 2, sc = (tid & 3) * 16;
@@ -100,6 +102,43 @@ __global__ __launch_bounds__(256) void energy_i8_kernel(const int8_t *__restrict
   }
 }
 
+__global__ __launch_bounds__(256) void energy_i8_kernel(const int8_t *__restrict__ J8,
+                                                        const int8_t *__restrict__ S8,
+                                                        const int8_t *__restrict__ h8,
+                                                        int32_t *__restrict__ acc_out, int ld) {
+  energy_i8_tile(J8, S8, h8, acc_out, ld, blockIdx.x * EBM, blockIdx.y * EBN);
+}
+
+// Batch: work item (instance, row tile, column tile) over the instances with
+// integer couplings; instance i's spins start at S8 + d.soff and its
+// accumulators at acc + i * r_pad.
+__global__ __launch_bounds__(256) void energy_i8_batch_kernel(const EBatchDesc *__restrict__ descs,
+                                                              const int4 *__restrict__ items,
+                                                              const int8_t *__restrict__ S8,
+                                                              int32_t *__restrict__ acc,
+                                                              int r_pad) {
+  const int4 it = items[blockIdx.x];
+  const EBatchDesc d = descs[it.x];
+  energy_i8_tile(d.J8, S8 + d.soff, nullptr, acc + (size_t)it.x * r_pad, d.n_pad, it.y * EBM,
+                 it.z * EBN);
+}
+
+// Batch finalisation: entry i * r + col of the outputs for every instance
+// with integer couplings (J8 set in its descriptor), accumulators reset.
+__global__ void energy_i8_batch_finalize_kernel(int32_t *acc, const EBatchDesc *__restrict__ descs,
+                                                int n_inst, int r, int r_pad, int32_t *e_int,
+                                                double *e_real) {
+  const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)n_inst * r) return;
+  const int i = (int)(idx / r), col = (int)(idx % r);
+  if (!descs[i].J8) return;
+  int32_t *a = acc + (size_t)i * r_pad + col;
+  const int32_t e = -(*a / 2);
+  if (e_int) e_int[idx] = e;
+  if (e_real) e_real[idx] = (double)e;
+  *a = 0;
+}
+
 __global__ void sign_kernel(const float4 *__restrict__ q, char4 *__restrict__ s, int64_t n4) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n4;
        i += (int64_t)gridDim.x * blockDim.x) {
@@ -143,6 +182,17 @@ hipError_t launch_energy_i8(const int8_t *J8, const int8_t *S8, const int8_t *h8
 hipError_t launch_energy_i8_finalize(int32_t *acc, int32_t r, int32_t *e_int, double *e_real,
                                      hipStream_t s) {
   energy_i8_finalize_kernel<<<(r + 255) / 256, 256, 0, s>>>(acc, r, e_int, e_real);
+  return hipGetLastError();
+}
+
+hipError_t launch_energy_i8_batch(const EBatchDesc *descs, const int4 *items, int32_t n_items,
+                                  const int8_t *S8, int32_t *acc, int32_t n_inst, int32_t r,
+                                  int32_t r_pad, int32_t *e_int, double *e_real, hipStream_t s) {
+  if (n_items > 0)
+    energy_i8_batch_kernel<<<n_items, 256, 0, s>>>(descs, items, S8, acc, r_pad);
+  const int64_t total = (int64_t)n_inst * r;
+  energy_i8_batch_finalize_kernel<<<(int)((total + 255) / 256), 256, 0, s>>>(
+      acc, descs, n_inst, r, r_pad, e_int, e_real);
   return hipGetLastError();
 }
 

@@ -146,6 +146,21 @@ hipError_t launch_split_planes(const float *q, uint16_t *planes, int64_t total, 
 
 // G = J.sign(Q) in FP32, per-row-tile partial sums of s_i (G_i + 2 h_i):
 // part[row_tile][r].  BM is fixed at 64 rows.
+// Batched energies: one descriptor per instance; work items (instance, row
+// tile, column tile) over 64 x 64 tiles, one list per path.
+struct EBatchDesc {
+  const int8_t *J8;   // integer couplings (exact int32 energy), or null: real path
+  const float *J;     // FP32 couplings
+  int64_t soff;       // offset of the instance's state in the batch's state buffers
+  int32_t n_pad;      // instance rows (multiple of 64)
+  int32_t part_row;   // first row of its row-tile partials (real path)
+};
+hipError_t launch_energy_i8_batch(const EBatchDesc *descs, const int4 *items, int32_t n_items,
+                                  const int8_t *S8, int32_t *acc, int32_t n_inst, int32_t r,
+                                  int32_t r_pad, int32_t *e_int, double *e_real, hipStream_t s);
+hipError_t launch_energy_f32_batch(const EBatchDesc *descs, const int4 *items, int32_t n_items,
+                                   const float *q, float *part, int32_t n_inst, int32_t r,
+                                   int32_t r_pad, double *e_real, hipStream_t s);
 hipError_t launch_energy_f32_partial(const float *J, const float *q, const float *h,
                                      float *part, int32_t n_pad, int32_t r_pad,
                                      hipStream_t s);

@@ -108,6 +108,15 @@ struct si_ctx {
   int4 *b_items = nullptr;
   int32_t b_max_npad = 0;
   int64_t b_total_n = 0;
+  int64_t b_stot = 0;                     // elements of one state buffer (all instances)
+  std::vector<int64_t> b_soff;            // offset of instance i in the state buffers
+  // grouped energy: one descriptor per instance; work items of the integer
+  // instances first (eb_n_i8 of them), then those of the real ones
+  std::vector<EBatchDesc> eb_desc_host;
+  std::vector<int4> eb_items_host;
+  EBatchDesc *eb_desc = nullptr;
+  int4 *eb_items = nullptr;
+  int32_t eb_n_i8 = 0, eb_n_f32 = 0;
   // batched precision form: per-instance J format (1: FP8, 2: hi + lo BF16)
   bool b_lowp = false;
   std::vector<int32_t> b_fmt;
@@ -557,10 +566,10 @@ si_status spring_ising_init_batch(si_ctx **out, int32_t n_inst, const int32_t *n
   }
   BINIT_HIP(c->alloc(&c->dt, prm->total_steps));
   BINIT_HIP(c->alloc(&c->zeta, prm->total_steps));
-  BINIT_HIP(c->alloc(&c->S8, (int64_t)c->b_max_npad * c->r_pad));
-  BINIT_HIP(c->alloc(&c->eacc, c->r_pad));
-  BINIT_HIP(c->alloc(&c->epart, (int64_t)(c->b_max_npad / 64) * c->r_pad));
-  BINIT_HIP(launch_zero_i32(c->eacc, c->r_pad, c->stream));
+  c->b_stot = stot;
+  BINIT_HIP(c->alloc(&c->S8, stot));  // sign(q) of every instance, in the state layout
+  BINIT_HIP(c->alloc(&c->eacc, (int64_t)n_inst * c->r_pad));
+  BINIT_HIP(launch_zero_i32(c->eacc, (int64_t)n_inst * c->r_pad, c->stream));
   int64_t jo = 0, j8o = 0, so = 0;
   c->b_J.resize(n_inst);
   c->b_J8.resize(n_inst);
@@ -569,6 +578,7 @@ si_status spring_ising_init_batch(si_ctx **out, int32_t n_inst, const int32_t *n
     c->b_p[b].resize(n_inst);
   }
   c->b_desc_host.resize(n_inst);
+  c->b_soff.resize(n_inst);
   if (lowp) {
     c->bb_desc_host.resize(n_inst);
     for (int b = 0; b < 2; ++b) c->b_qb[b].resize(n_inst);
@@ -580,6 +590,7 @@ si_status spring_ising_init_batch(si_ctx **out, int32_t n_inst, const int32_t *n
     c->b_J8[i] = c->b_jmax[i] >= 0 ? J8all + j8o : nullptr;
     jo += nn;
     if (c->b_jmax[i] >= 0) j8o += nn;
+    c->b_soff[i] = so;
     c->b_q[0][i] = sbuf[0] + so;
     c->b_q[1][i] = sbuf[1] + so;
     c->b_p[0][i] = sbuf[2] + so;
@@ -625,6 +636,30 @@ si_status spring_ising_init_batch(si_ctx **out, int32_t n_inst, const int32_t *n
   for (int32_t i : order)
     for (int32_t rt = 0; rt < c->b_npad[i] / item_rows; ++rt)
       for (int32_t ct = 0; ct < c->r_pad / BATCH_BN; ++ct) c->b_items_host.push_back(int4{i, rt, ct, 0});
+  // grouped energy: exact int32 where the couplings are integer and the sum
+  // cannot overflow, else the FP32 coupling sum; 64 x 64 tiles
+  c->eb_desc_host.resize(n_inst);
+  int32_t part_rows = 0;
+  for (int pass = 0; pass < 2; ++pass)
+    for (int32_t i : order) {
+      const int64_t bound = (int64_t)n[i] * n[i] * (c->b_jmax[i] < 0 ? 0 : c->b_jmax[i]);
+      const bool exact = c->b_J8[i] != nullptr && bound < (1LL << 31);
+      if (exact != (pass == 0)) continue;
+      c->eb_desc_host[i] = EBatchDesc{exact ? c->b_J8[i] : nullptr, c->b_J[i], c->b_soff[i],
+                                      c->b_npad[i], exact ? 0 : part_rows};
+      if (!exact) part_rows += c->b_npad[i] / 64;
+      for (int32_t rt = 0; rt < c->b_npad[i] / 64; ++rt)
+        for (int32_t ct = 0; ct < c->r_pad / 64; ++ct) c->eb_items_host.push_back(int4{i, rt, ct, 0});
+      (pass == 0 ? c->eb_n_i8 : c->eb_n_f32) += (c->b_npad[i] / 64) * (c->r_pad / 64);
+    }
+  BINIT_HIP(c->alloc(&c->epart, (int64_t)(part_rows > 0 ? part_rows : 1) * c->r_pad));
+  BINIT_HIP(c->alloc(&c->eb_desc, n_inst));
+  BINIT_HIP(c->alloc(&c->eb_items, (int64_t)c->eb_items_host.size()));
+  BINIT_HIP(hipMemcpyAsync(c->eb_desc, c->eb_desc_host.data(), sizeof(EBatchDesc) * n_inst,
+                           hipMemcpyHostToDevice, c->stream));
+  BINIT_HIP(hipMemcpyAsync(c->eb_items, c->eb_items_host.data(),
+                           sizeof(int4) * c->eb_items_host.size(), hipMemcpyHostToDevice,
+                           c->stream));
   BINIT_HIP(c->alloc(&c->b_desc, n_inst));
   BINIT_HIP(c->alloc(&c->b_items, (int64_t)c->b_items_host.size()));
   BINIT_HIP(hipMemcpyAsync(c->b_desc, c->b_desc_host.data(), sizeof(BatchDesc) * n_inst,
@@ -1129,38 +1164,30 @@ si_status spring_ising_autotune(si_ctx *c, int32_t steps, int32_t *best_tile, fl
 
 // ---- batched-context variants (instances concatenated in caller layouts) ----
 static si_status batch_spins(si_ctx *c, int8_t *s) {
-  for (int32_t i = 0; i < c->n_inst; ++i) {
-    SI_HIP(c, launch_sign(c->b_q[c->cur][i], c->S8, c->b_npad[i], c->r_pad, c->stream));
-    SI_HIP(c, launch_unpack_spins(c->S8, c->b_n[i], c->r, s + c->b_xoff[i], c->b_npad[i],
-                                  c->stream));
-  }
+  SI_HIP(c, launch_sign(c->b_q[c->cur][0], c->S8, (int32_t)(c->b_stot / c->r_pad), c->r_pad,
+                        c->stream));
+  for (int32_t i = 0; i < c->n_inst; ++i)
+    SI_HIP(c, launch_unpack_spins(c->S8 + c->b_soff[i], c->b_n[i], c->r, s + c->b_xoff[i],
+                                  c->b_npad[i], c->stream));
   return SI_OK;
 }
 
+// Every instance in at most two grouped launches (plus their finalisations):
+// the int8 matrix-core energy for the integer instances, the FP32 coupling
+// sum for the others.
 static si_status batch_energy(si_ctx *c, int32_t *e_int, double *e_real) {
-  std::vector<char> exact(c->n_inst);
-  for (int32_t i = 0; i < c->n_inst; ++i) {
-    const int64_t bound = (int64_t)c->b_n[i] * c->b_n[i] * (c->b_jmax[i] < 0 ? 0 : c->b_jmax[i]);
-    exact[i] = c->b_J8[i] != nullptr && bound < (1LL << 31);
-    if (e_int && !exact[i])
+  for (int32_t i = 0; i < c->n_inst; ++i)
+    if (e_int && !c->eb_desc_host[i].J8)
       return fail(SI_ERR_UNSUPPORTED, "energy: instance %d has non-integer couplings", i);
+  const float *q = c->b_q[c->cur][0];  // state of instance 0 starts the buffer
+  if (c->eb_n_i8) {
+    SI_HIP(c, launch_sign(q, c->S8, (int32_t)(c->b_stot / c->r_pad), c->r_pad, c->stream));
+    SI_HIP(c, launch_energy_i8_batch(c->eb_desc, c->eb_items, c->eb_n_i8, c->S8, c->eacc,
+                                     c->n_inst, c->r, c->r_pad, e_int, e_real, c->stream));
   }
-  for (int32_t i = 0; i < c->n_inst; ++i) {
-    int32_t *ei = e_int ? e_int + (int64_t)i * c->r : nullptr;
-    double *er = e_real ? e_real + (int64_t)i * c->r : nullptr;
-    const float *q = c->b_q[c->cur][i];
-    if (exact[i]) {
-      SI_HIP(c, launch_sign(q, c->S8, c->b_npad[i], c->r_pad, c->stream));
-      SI_HIP(c, launch_energy_i8(c->b_J8[i], c->S8, nullptr, c->eacc, c->b_npad[i], c->r_pad,
-                                 c->stream));
-      SI_HIP(c, launch_energy_i8_finalize(c->eacc, c->r, ei, er, c->stream));
-    } else if (er) {
-      SI_HIP(c, launch_energy_f32_partial(c->b_J[i], q, nullptr, c->epart, c->b_npad[i], c->r_pad,
-                                          c->stream));
-      SI_HIP(c, launch_energy_f32_finalize(c->epart, c->b_npad[i] / 64, c->r, c->r_pad, er,
-                                           c->stream));
-    }
-  }
+  if (c->eb_n_f32 && e_real)
+    SI_HIP(c, launch_energy_f32_batch(c->eb_desc, c->eb_items + c->eb_n_i8, c->eb_n_f32, q,
+                                      c->epart, c->n_inst, c->r, c->r_pad, e_real, c->stream));
   return SI_OK;
 }
 

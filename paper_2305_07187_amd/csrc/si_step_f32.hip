@@ -355,13 +355,12 @@ hipError_t launch_step_f32(int32_t tile, const StepArgs &a, hipStream_t s) {
 // ---------------------------------------------------------------------------
 using ECfg = F32Cfg<64, 64, 2, 2, 32, 32>;
 
-__global__ __launch_bounds__(256) void energy_f32_partial_kernel(const float *J, const float *q,
-                                                                 const float *h, float *part,
-                                                                 int ld, int r_pad) {
+// One 64 x 64 tile: the partial sums of this tile's rows for its 64
+// replicas, written to part_row[n0 ..].
+__device__ __forceinline__ void energy_f32_tile(const float *J, const float *q, const float *h,
+                                                float *part_row, int ld, int m0, int n0) {
   __shared__ __attribute__((aligned(16))) float smem[ECfg::LDS_FLOATS];
   __shared__ float red[ECfg::WM][ECfg::BN];
-  const int m0 = blockIdx.x * ECfg::BM;
-  const int n0 = blockIdx.y * ECfg::BN;
   ECfg::acc_t acc[ECfg::TM][ECfg::TN];
   f32_mainloop<ECfg, B_SIGN>(J, q, ld, ld, m0, n0, acc, smem);
   const int lane = threadIdx.x & 63;
@@ -390,14 +389,21 @@ __global__ __launch_bounds__(256) void energy_f32_partial_kernel(const float *J,
     float s = 0.f;
 #pragma unroll
     for (int w = 0; w < ECfg::WM; ++w) s += red[w][threadIdx.x];
-    part[(size_t)blockIdx.x * r_pad + n0 + threadIdx.x] = s;
+    part_row[n0 + threadIdx.x] = s;
   }
 }
-__global__ void energy_f32_finalize_kernel(const float *part, int n_tiles, int r, int r_pad,
-                                           double *e, float scale) {
-  const int col = blockIdx.x * blockDim.x + threadIdx.x;
-  if (col >= r) return;
-  // Neumaier-compensated FP32 sum over the row tiles, in fixed order.
+
+__global__ __launch_bounds__(256) void energy_f32_partial_kernel(const float *J, const float *q,
+                                                                 const float *h, float *part,
+                                                                 int ld, int r_pad) {
+  energy_f32_tile(J, q, h, part + (size_t)blockIdx.x * r_pad, ld, blockIdx.x * ECfg::BM,
+                  blockIdx.y * ECfg::BN);
+}
+
+// Neumaier-compensated FP32 sum of one replica's row-tile partials (stride
+// r_pad), in fixed order.
+__device__ __forceinline__ double energy_f32_sum(const float *part, int n_tiles, int r_pad,
+                                                 int col, float scale) {
   float s = 0.f, comp = 0.f;
   for (int t = 0; t < n_tiles; ++t) {
     const float x = part[(size_t)t * r_pad + col];
@@ -408,7 +414,39 @@ __global__ void energy_f32_finalize_kernel(const float *part, int n_tiles, int r
       comp += (x - y) + s;
     s = y;
   }
-  e[col] = (double)scale * ((double)s + (double)comp);
+  return (double)scale * ((double)s + (double)comp);
+}
+
+__global__ void energy_f32_finalize_kernel(const float *part, int n_tiles, int r, int r_pad,
+                                           double *e, float scale) {
+  const int col = blockIdx.x * blockDim.x + threadIdx.x;
+  if (col >= r) return;
+  e[col] = energy_f32_sum(part, n_tiles, r_pad, col, scale);
+}
+
+// Batch: work item (instance, row tile, column tile) over the instances with
+// real couplings; instance i's positions start at q + d.soff and its
+// row-tile partials at part + d.part_row * r_pad.
+__global__ __launch_bounds__(256) void energy_f32_batch_kernel(const EBatchDesc *__restrict__ descs,
+                                                               const int4 *__restrict__ items,
+                                                               const float *q, float *part,
+                                                               int r_pad) {
+  const int4 it = items[blockIdx.x];
+  const EBatchDesc d = descs[it.x];
+  energy_f32_tile(d.J, q + d.soff, nullptr, part + ((size_t)d.part_row + it.y) * r_pad, d.n_pad,
+                  it.y * ECfg::BM, it.z * ECfg::BN);
+}
+
+__global__ void energy_f32_batch_finalize_kernel(const float *part,
+                                                 const EBatchDesc *__restrict__ descs, int n_inst,
+                                                 int r, int r_pad, double *e) {
+  const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)n_inst * r) return;
+  const int i = (int)(idx / r), col = (int)(idx % r);
+  const EBatchDesc d = descs[i];
+  if (d.J8) return;
+  e[idx] = energy_f32_sum(part + (size_t)d.part_row * r_pad, d.n_pad / ECfg::BM, r_pad, col,
+                          -0.5f);
 }
 
 // ---------------------------------------------------------------------------
@@ -498,6 +536,17 @@ hipError_t launch_energy_f32_partial(const float *J, const float *q, const float
   if (n_pad % ECfg::BM || r_pad % ECfg::BN) return hipErrorInvalidValue;
   dim3 grid(n_pad / ECfg::BM, r_pad / ECfg::BN);
   energy_f32_partial_kernel<<<grid, 256, 0, s>>>(J, q, h, part, n_pad, r_pad);
+  return hipGetLastError();
+}
+
+hipError_t launch_energy_f32_batch(const EBatchDesc *descs, const int4 *items, int32_t n_items,
+                                   const float *q, float *part, int32_t n_inst, int32_t r,
+                                   int32_t r_pad, double *e_real, hipStream_t s) {
+  if (n_items > 0)
+    energy_f32_batch_kernel<<<n_items, 256, 0, s>>>(descs, items, q, part, r_pad);
+  const int64_t total = (int64_t)n_inst * r;
+  energy_f32_batch_finalize_kernel<<<(int)((total + 255) / 256), 256, 0, s>>>(
+      part, descs, n_inst, r, r_pad, e_real);
   return hipGetLastError();
 }
 
