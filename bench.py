@@ -86,12 +86,13 @@ def cpu_baseline(budget_s: float = 15.0):
                       f"{el:.1f} s), extrapolated per iteration"}
 
 
-def batched_form(si, steps=300, n_inst=256, r=64, sequential=True):
+def batched_form(si, steps=300, n_inst=256, r=64, sequential=True, time_to_target=True):
     """The batched configuration (256 uneven instances, N in [64, 4096], half
     +-1 and half Gaussian, R = 64): ms per step of all instances together,
     batched in FP32 and in the BF16 form (FP8 / hi + lo J), and (unless
     sequential is off) the same instances stepped one after another as
-    single FP32 contexts."""
+    single FP32 contexts; unless time_to_target is off, the time to a target
+    energy of both batched forms."""
     import torch
 
     from paper_2305_07187_amd import instances
@@ -112,9 +113,10 @@ def batched_form(si, steps=300, n_inst=256, r=64, sequential=True):
         out[f"{form}_batched_ms_per_step"] = 1000.0 * (time.perf_counter() - t0) / steps
         out[f"{form}_kernel"] = b.info()["kernel_name"]
         b.close()
+    if time_to_target:
+        out["time_to_target"] = batched_time_to_target(si, Js, xs)
     if not sequential:
         return out
-    out["time_to_target"] = batched_time_to_target(si, Js, xs)
     seq = 0.0
     for J, x in zip(Js, xs):
         m = si.SpringIsing(J, x, total_steps=30)
@@ -273,6 +275,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-form timing")
     ap.add_argument("--batched-steps", type=int, default=300, help=argparse.SUPPRESS)
     ap.add_argument("--no-sequential", action="store_true", help=argparse.SUPPRESS)
+    ap.add_argument("--no-batched-ttt", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--no-differentiation", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--iters", type=int, default=ITERS, help=argparse.SUPPRESS)
     # other shapes, for profiling the precision configurations (not bench lines)
@@ -402,7 +405,8 @@ def main():
     model.close()
     if fp32_line and not args.no_batched and (n, r, args.couplings) == (N, R, "pm1"):
         out["batched_form"] = batched_form(si, steps=args.batched_steps,
-                                           sequential=not args.no_sequential)
+                                           sequential=not args.no_sequential,
+                                           time_to_target=not args.no_batched_ttt)
         if not args.no_differentiation:
             out["differentiation_form"] = differentiation_form(si)
     if not args.no_cpu_baseline:
