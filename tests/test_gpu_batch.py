@@ -99,6 +99,47 @@ def test_batch_energies_and_layout():
     b.close()
 
 
+def test_batch_energy_paths():
+    # The grouped energy of a batch mixing the three cases: +-1 couplings
+    # (int8 matrix cores, exact), integer couplings whose sum could pass
+    # 2^31 (N^2 max|J| >= 2^31: FP32 path although J is integer) and
+    # Gaussian couplings (FP32 path).  Two calls in a row must agree (the
+    # integer accumulators are reset by each call).
+    import torch
+    si = ensure_built()
+    announce("batch energy paths: +-1, integer 127 at N=4200, Gaussian")
+    r = 8
+    Js = [instances.make_pm1(300, 31), 127.0 * instances.make_pm1(4200, 32),
+          instances.make_gauss(200, 33)]
+    Js = [J.astype(np.float32) for J in Js]
+    states = [instances.random_state(J.shape[0], r, 50 + i) for i, J in enumerate(Js)]
+    b = si.SpringIsingBatch([to_dev(J) for J in Js], [to_dev(x) for x in states], total_steps=4)
+    with pytest.raises(si.SpringIsingError) as err:
+        b.energy(exact=True)
+    assert err.value.status == si.SI_ERR_UNSUPPORTED
+    e1 = [e.cpu().numpy() for e in b.energy(exact=False)]
+    e2 = [e.cpu().numpy() for e in b.energy(exact=False)]
+    torch.cuda.synchronize()
+    for i, J in enumerate(Js):
+        n = J.shape[0]
+        np.testing.assert_array_equal(e1[i], e2[i])
+        ref = oracle.ising_energy(J.astype(np.float64), oracle.spins(states[i].T))
+        if i == 0:
+            np.testing.assert_array_equal(e1[i], ref)
+        else:
+            bound = n * 2.0 ** -24 * np.abs(J).astype(np.float64).sum() + 1e-6
+            assert np.all(np.abs(e1[i] - ref) <= bound), (i, np.abs(e1[i] - ref).max(), bound)
+    b.close()
+    # the +-1 instance alone in a batch: exact energies, twice
+    b = si.SpringIsingBatch([to_dev(Js[0])], [to_dev(states[0])], total_steps=4)
+    ea = b.energy(exact=True)[0].cpu().numpy()
+    eb = b.energy(exact=True)[0].cpu().numpy()
+    ref = oracle.ising_energy(Js[0].astype(np.float64), oracle.spins(states[0].T))
+    np.testing.assert_array_equal(ea, ref)
+    np.testing.assert_array_equal(eb, ref)
+    b.close()
+
+
 def test_batch_full_workload_generated_on_device():
     # 256 instances, N uniform in [64, 4096], half +-1, half Gaussian, R=64
     import time
