@@ -346,6 +346,9 @@ class SpringIsingBatch:
     def step(self):
         spring_ising_step(self.ctx)
 
+    def set_graph(self, min_steps):
+        spring_ising_set_graph(self.ctx, min_steps)
+
     def _split(self, flat):
         return [flat[self.offsets[i]:self.offsets[i + 1]].view(self.r, n)
                 for i, n in enumerate(self.ns)]

@@ -54,14 +54,22 @@ def test_graph_on_batch():
     xs = [to_dev(instances.make_x0(n, 64, i)) for i, (n, k) in enumerate(specs)]
     a = si.SpringIsingBatch(Js, xs, total_steps=100)
     a.run(100)
-    xa, _, _ = a.state()
+    xa, pa, _ = a.state()
+    ea = a.energy()
     b = si.SpringIsingBatch(Js, xs, total_steps=100)
-    si.spring_ising_set_graph(b.ctx, 10)
-    b.run(100)
-    xb, _, _ = b.state()
-    torch.cuda.synchronize()
-    for u, v in zip(xa, xb):
-        assert torch.equal(u, v)
+    b.set_graph(10)
+    for rep in range(3):
+        # restarts of the schedule replay the graph captured by the first run
+        b.set_state(xs, None, 0)
+        b.run(100)
+        xb, pb, t = b.state()
+        eb = b.energy()  # eager work between replays
+        torch.cuda.synchronize()
+        assert t == 100
+        for u, v in zip(xa + pa + ea, xb + pb + eb):
+            assert torch.equal(u, v), rep
+    a.close()
+    b.close()
 
 
 @pytest.mark.parametrize("precision", ["fp32", "bf16x_bf16j"])
