@@ -17,8 +17,11 @@ FP32 final energies; each form runs the same schedule with the exact energy
 of every replica checked every 50 steps (check cost included, timed with
 HIP events on the stream the kernels run on) and its time-to-target is the
 event time of the first check with a replica at or below the target.
+The precision form's full configurations (R = 2048: FP8 J at N = 2000, hi +
+lo BF16 J at N = 8000) are timed per step against FP32 on the same shapes.
 The batched configuration (256 uneven instances, R = 64) is timed per step
-in FP32 and in the BF16 form, and against the same instances stepped one
+in FP32 and in the BF16 form (also as a graph replay), with a time to a
+per-instance target energy, and against the same instances stepped one
 after another; the differentiation configuration (schedule gradient at
 N = 2000, R = 64, 2000 steps) is timed beside its plain forward run.
 
@@ -183,6 +186,40 @@ def batched_time_to_target(si, Js, xs, steps=3000, every=100, rank=7):
                      "instances_at_target_at_end": int((mins[-1] <= targets).sum())}
     t32, t16 = out["fp32"]["ttt_s"], out["bf16x_mixedj"]["ttt_s"]
     out["bf16_speedup_vs_fp32"] = (t32 / t16) if (t32 and t16) else None
+    return out
+
+
+def precision_full_configurations(si, r=2048, total=5000, steps=200, warm=20):
+    """The precision form at its full configurations (R = 2048, the 5000-step
+    schedule): FP8 J at N = 2000 (+-1 couplings) and hi + lo BF16 J at
+    N = 8000 (Gaussian couplings), each against the plain FP32 step on the
+    same shape.  HIP-event time of `steps` steps after `warm` warm-up steps."""
+    import torch
+
+    from paper_2305_07187_amd import instances
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    out = {"replicas": r, "schedule_steps": total, "steps_timed": steps}
+    for key, n, kind, form in (("fp8j_n2000", 2000, "pm1", "bf16x_fp8j"),
+                               ("hiloj_n8000", 8000, "gauss", "bf16x_hiloj")):
+        J = instances.make_J_torch(n, kind, 0, dev)
+        x0 = instances.make_x0_torch(n, r, 0, device=dev)
+        rec = {"n": n, "couplings": kind}
+        for prec in (form, "fp32"):
+            m = si.SpringIsing(J, x0, total_steps=total, precision=prec)
+            m.run(warm)
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            m.run(steps)
+            b.record(stream)
+            torch.cuda.synchronize()
+            ms = a.elapsed_time(b) / steps
+            rec[prec] = {"ms_per_step": ms, "spin_updates_per_s": n * r / (ms / 1000.0),
+                         "kernel": m.info()["kernel_name"]}
+            m.close()
+        rec["speedup_vs_fp32"] = rec["fp32"]["ms_per_step"] / rec[form]["ms_per_step"]
+        out[key] = rec
+        del J, x0
     return out
 
 
@@ -413,6 +450,8 @@ def main():
         out["time_to_target"] = {"target_energy": target, "check_every": CHECK_EVERY,
                                  "forms": forms}
     model.close()
+    if fp32_line and not args.no_forms and (n, r, args.couplings) == (N, R, "pm1"):
+        out["precision_full_configurations"] = precision_full_configurations(si)
     if fp32_line and not args.no_batched and (n, r, args.couplings) == (N, R, "pm1"):
         out["batched_form"] = batched_form(si, steps=args.batched_steps,
                                            sequential=not args.no_sequential,
