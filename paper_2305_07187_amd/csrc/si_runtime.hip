@@ -274,15 +274,18 @@ static int32_t choose_tile_bf16(int32_t n, int32_t r, int num_cus, int32_t preci
   // workgroup of that size, then 128x128 (for the three-plane form the
   // two-slab ring of eight waves) and 64x64 direct-to-LDS rings, then
   // register-staged tiles as the fallback for small problems.
-  static const int32_t pref_bf16j[] = {16, 18, 8, 7, 11, 10, 1, 2, 3};
-  static const int32_t pref_fp8j[] = {19, 14, 9, 13, 1, 6, 2, 3};
+  static const int32_t pref_bf16j[] = {16, 18, 23, 8, 7, 11, 10, 1, 2, 3};
+  static const int32_t pref_fp8j[] = {19, 14, 23, 9, 13, 1, 6, 2, 3};
   static const int32_t pref_hilo[] = {20, 18, 7, 10, 11, 1, 2, 3};
   static const int32_t pref_exact[] = {21, 22, 11, 8, 7, 1, 2, 3};
-  const int32_t *order = pref_bf16j;
-  int count = 9;
-  if (precision == SI_PREC_BF16X_FP8J) { order = pref_fp8j; count = 8; }
-  if (precision == SI_PREC_BF16X_HILOJ) { order = pref_hilo; count = 8; }
-  if (precision == SI_PREC_BF16X3_EXACTJ) { order = pref_exact; count = 8; }
+#define SI_PREF(a) order = a, count = (int)(sizeof a / sizeof a[0])
+  const int32_t *order;
+  int count;
+  SI_PREF(pref_bf16j);
+  if (precision == SI_PREC_BF16X_FP8J) SI_PREF(pref_fp8j);
+  if (precision == SI_PREC_BF16X_HILOJ) SI_PREF(pref_hilo);
+  if (precision == SI_PREC_BF16X3_EXACTJ) SI_PREF(pref_exact);
+#undef SI_PREF
   int32_t best = 1;
   int64_t best_tiles = -1;
   for (int c = 0; c < count; ++c) {

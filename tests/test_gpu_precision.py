@@ -163,9 +163,9 @@ def test_fp8_and_bf16_j_identical():
 
 
 @pytest.mark.parametrize("precision,group", [
-    ("bf16x_bf16j", (7, 8, 9, 10, 11, 12, 13, 15, 16, 17, 18, 20, 21, 22)),
+    ("bf16x_bf16j", (7, 8, 9, 10, 11, 12, 13, 15, 16, 17, 18, 20, 21, 22, 23)),
     ("bf16x_bf16j", (1, 2, 3, 4, 5, 6)),
-    ("bf16x_fp8j", (9, 13, 14, 19)),
+    ("bf16x_fp8j", (9, 13, 14, 19, 23)),
     ("bf16x_hiloj", (7, 8, 9, 10, 11, 12, 18, 20, 21, 22)),
     ("bf16x3_exactj", (7, 8, 11, 21, 22))])
 def test_bf16_tiles_agree(precision, group):
@@ -194,7 +194,8 @@ def test_bf16_tiles_agree(precision, group):
 
 
 @pytest.mark.parametrize("precision,group", [
-    ("bf16x_bf16j", (16, 18, 20, 21)),
+    ("bf16x_bf16j", (16, 18, 20, 21, 23)),
+    ("bf16x_fp8j", (9, 19, 23)),
     ("bf16x_hiloj", (18, 20, 21)),
     ("bf16x3_exactj", (11, 21, 22))])
 def test_large_bf16_tiles_agree_ragged(precision, group):
