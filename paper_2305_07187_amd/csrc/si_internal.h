@@ -108,7 +108,7 @@ hipError_t launch_step_batch_f32(const StepArgs &a, const BatchDesc *descs, cons
                                  int32_t n_items, int32_t cur, hipStream_t s);
 
 // Step on the BF16 matrix cores (precision forms).
-constexpr int32_t TILE_BF16_LAST = 23;
+constexpr int32_t TILE_BF16_LAST = 24;
 TileShape tile_shape_bf16(int32_t tile);
 struct BStepArgs {
   const void *Ja;         // J plane: bf16 or fp8 [n_pad][n_pad]

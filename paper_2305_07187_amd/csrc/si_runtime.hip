@@ -277,7 +277,7 @@ static int32_t choose_tile_bf16(int32_t n, int32_t r, int num_cus, int32_t preci
   static const int32_t pref_bf16j[] = {16, 18, 23, 8, 7, 11, 10, 1, 2, 3};
   static const int32_t pref_fp8j[] = {19, 14, 23, 9, 13, 1, 6, 2, 3};
   static const int32_t pref_hilo[] = {20, 18, 7, 10, 11, 1, 2, 3};
-  static const int32_t pref_exact[] = {21, 22, 11, 8, 7, 1, 2, 3};
+  static const int32_t pref_exact[] = {21, 22, 24, 11, 8, 7, 1, 2, 3};
 #define SI_PREF(a) order = a, count = (int)(sizeof a / sizeof a[0])
   const int32_t *order;
   int count;

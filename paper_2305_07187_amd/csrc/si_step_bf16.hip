@@ -569,7 +569,8 @@ static hipError_t launch_bd(const BStepArgs &a, hipStream_t s) {
 // Tile 22 is the two-slab ring that fits eight waves on a 128x128 block of
 // the three-plane form (its three-slab ring would exceed the LDS); tile 23
 // gives the single-plane forms eight waves on one 128x64 block per CU when
-// the problem has that many blocks (N = 2000, R = 1024).
+// the problem has that many blocks (N = 2000, R = 1024), and tile 24 the
+// same for the three-plane form over 64-deep slabs.
 #define SI_BF16_TILES(X)         \
   X(1, 64, 64, 2, 2, 64, 0)      \
   X(2, 64, 128, 2, 2, 64, 0)     \
@@ -593,7 +594,8 @@ static hipError_t launch_bd(const BStepArgs &a, hipStream_t s) {
   X(20, 128, 256, 2, 4, 64, 2)   \
   X(21, 256, 128, 4, 2, 64, 2)   \
   X(22, 128, 128, 2, 4, 64, 2)   \
-  X(23, 128, 64, 4, 2, 128, 3)
+  X(23, 128, 64, 4, 2, 128, 3)   \
+  X(24, 128, 64, 4, 2, 64, 3)
 
 TileShape tile_shape_bf16(int32_t tile) {
   switch (tile) {
