@@ -157,7 +157,7 @@ si_status spring_ising_init(si_ctx **out, int32_t n, int32_t r, const float *J,
  *       symmetric zero-diagonal matrix.
  *   x0: host array of n_inst device pointers, instance i r*n[i] floats;
  *       initial momenta are 0.
- * Precisions: FP32 (64x64 tiles, instances padded to 64), or the BF16 forms
+ * Precisions: FP32 (128x64 tiles, instances padded to 128), or the BF16 forms
  * BF16X_FP8J (every J exact in FP8), BF16X_HILOJ and BF16X_MIXEDJ (FP8 J
  * where exact, hi + lo BF16 J otherwise), on 128x64 tiles with instances
  * padded to 128; BF16X_BF16J and BF16X3_EXACTJ: SI_ERR_UNSUPPORTED.  Each

@@ -98,7 +98,7 @@ hipError_t launch_resident_f32(int32_t tile, const StepArgs &a, const ResidentAr
                                hipStream_t s);
 
 // Batched form: per-instance buffers and the work list of one grouped launch.
-constexpr int BATCH_BM = 64, BATCH_BN = 64;
+constexpr int BATCH_BM = 128, BATCH_BN = 64;
 struct BatchDesc {
   const float *J;         // [n_pad][n_pad]
   float *q0, *q1, *p0, *p1;  // [r_pad][n_pad] ping-pong state

@@ -482,7 +482,7 @@ si_status spring_ising_init_batch(si_ctx **out, int32_t n_inst, const int32_t *n
   if (st != SI_OK) return st;
   if (prm->precision == SI_PREC_BF16X_BF16J || prm->precision == SI_PREC_BF16X3_EXACTJ)
     return fail(SI_ERR_UNSUPPORTED, "init_batch: precision %d has no batched form", prm->precision);
-  if (prm->tile != 0) return fail(SI_ERR_INVALID, "init_batch: the batch uses fixed 64x64 tiles");
+  if (prm->tile != 0) return fail(SI_ERR_INVALID, "init_batch: the batch uses fixed tiles");
   const bool lowp = prm->precision != SI_PREC_FP32;
   for (int32_t i = 0; i < n_inst; ++i) {
     if (n[i] < 1 || n[i] > 65536) return fail(SI_ERR_INVALID, "init_batch: n[%d]=%d", i, n[i]);

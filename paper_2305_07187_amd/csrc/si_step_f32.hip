@@ -319,8 +319,10 @@ hipError_t launch_resident_f32(int32_t tile, const StepArgs &a, const ResidentAr
   }
 }
 
-// Batched tiles: 64 x 64, 32x32x2 MFMA, direct-to-LDS ring (4 stages).
-using BatchCfg = F32Cfg<BATCH_BM, BATCH_BN, 2, 2, 32, 32, 4, 1>;
+// Batched tiles: 128 x 64 (eight waves of 32 x 32), 32x32x2 MFMA, direct-to-LDS
+// ring (4 stages); the same contraction order as every single-instance
+// direct-to-LDS tile with one accumulator chain.
+using BatchCfg = F32Cfg<BATCH_BM, BATCH_BN, 4, 2, 32, 32, 4, 1>;
 
 hipError_t launch_step_batch_f32(const StepArgs &a, const BatchDesc *descs, const int4 *items,
                                  int32_t n_items, int32_t cur, hipStream_t s) {
