@@ -272,8 +272,9 @@ static int32_t choose_tile_bf16(int32_t n, int32_t r, int num_cus, int32_t preci
   // 256x128 with a double-buffered ring for the multi-plane forms, whose
   // fragment reads load the LDS most) once the problem gives every CU a
   // workgroup of that size, then 128x128 (for the three-plane form the
-  // two-slab ring of eight waves) and 64x64 direct-to-LDS rings, then
-  // register-staged tiles as the fallback for small problems.
+  // two-slab ring of eight waves), eight-wave 128x64 (single-plane and
+  // three-plane forms) and 64x64 direct-to-LDS rings, then register-staged
+  // tiles as the fallback for small problems.
   static const int32_t pref_bf16j[] = {16, 18, 23, 8, 7, 11, 10, 1, 2, 3};
   static const int32_t pref_fp8j[] = {19, 14, 23, 9, 13, 1, 6, 2, 3};
   static const int32_t pref_hilo[] = {20, 18, 7, 10, 11, 1, 2, 3};
