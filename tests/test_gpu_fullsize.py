@@ -27,13 +27,13 @@ R, S = 2048, 5000
 COLS = [0, 1, 777, 1500, 2047]
 
 
-def _one_step_sampled(si, Jd, J64, precision, seed):
+def _one_step_sampled(si, Jd, J64, precision, seed, r=R, cols=COLS):
     """One step at t = 37 from a random state; check sampled replicas."""
     import torch
     n = J64.shape[0]
-    x = instances.random_state(n, R, seed, scale=1.4)
-    p0 = instances.random_state(n, R, seed + 1, scale=1.9)
-    m = si.SpringIsing(Jd, to_dev(instances.make_x0(n, R, 0)), total_steps=S,
+    x = instances.random_state(n, r, seed, scale=1.4)
+    p0 = instances.random_state(n, r, seed + 1, scale=1.9)
+    m = si.SpringIsing(Jd, to_dev(instances.make_x0(n, r, 0)), total_steps=S,
                        precision=precision)
     m.set_state(to_dev(x), to_dev(p0), 37)
     m.step()
@@ -43,15 +43,16 @@ def _one_step_sampled(si, Jd, J64, precision, seed):
     m.close()
     dt, zeta = oracle_schedules(S)
     d, z = float(dt[37]), float(zeta[37])
-    xs = x[COLS].T.astype(np.float64)
-    Q, P = oracle.step(J64, xs, p0[COLS].T.astype(np.float64), d, z, qmax=QMAX)
+    xs = x[cols].T.astype(np.float64)
+    Q, P = oracle.step(J64, xs, p0[cols].T.astype(np.float64), d, z, qmax=QMAX)
     mag = np.abs(J64) @ np.abs(xs)
     jrel = 2.0 ** -16 if precision == "bf16x_hiloj" else 0.0
-    bound = d * z * mag * (2.0 ** -8 + jrel) * 1.01 + 4 * 2.0 ** -24 * (np.abs(P) + 2.0) \
+    qrel = 0.0 if precision == "bf16x3_exactj" else 2.0 ** -8  # BF16 positions
+    bound = d * z * mag * (qrel + jrel) * 1.01 + 4 * 2.0 ** -24 * (np.abs(P) + 2.0) \
         + d * z * mag * n * 2.0 ** -24
-    err = np.abs(pg.cpu().numpy()[COLS].T - P)
+    err = np.abs(pg.cpu().numpy()[cols].T - P)
     assert np.all(err <= bound), (err.max(), float(bound[np.argmax(err - bound)]))
-    assert np.abs(xg.cpu().numpy()[COLS].T - Q).max() <= 4e-7
+    assert np.abs(xg.cpu().numpy()[cols].T - Q).max() <= 4e-7
     announce(f"  {precision} ({name}) one-step momentum error vs FP64 oracle: max {err.max():.3e}, "
              f"relative {err.max() / np.abs(P).max():.3e}, worst fraction of bound "
              f"{float((err / bound).max()):.3f}")
@@ -86,6 +87,19 @@ def _compare_distributions(e_lp, e_32, label):
              f"({diff:+.2f} s.e.), best {e_lp.min():.2f} vs {e_32.min():.2f}, KS p = {ks:.3f}")
     assert abs(diff) < 4.0
     assert ks > 1e-3
+
+
+@pytest.mark.parametrize("precision", ["bf16x_fp8j", "bf16x_bf16j", "bf16x3_exactj"])
+def test_forms_one_step_at_benchmark_shape(precision):
+    # The time-to-target workload (N = 2000, R = 1024) in the launch
+    # configuration the library picks for it: one step on sampled replicas
+    # against the oracle (the three-plane split: FP32 accumulation only).
+    si = ensure_built()
+    n, r = 2000, 1024
+    announce(f"{precision} one step at N={n} R={r}, sampled replicas")
+    J = instances.make_pm1(n, 0)
+    _one_step_sampled(si, to_dev(J), J.astype(np.float64), precision, 41, r=r,
+                      cols=[0, 3, 511, 512, 1000, 1023])
 
 
 def test_fp8_pm1_full_configuration():
