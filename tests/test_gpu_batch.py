@@ -201,6 +201,43 @@ def test_bf16_batch_equals_standalone_runs():
     b.close()
 
 
+@pytest.mark.parametrize("precision", ["fp32", "bf16x_mixedj"])
+def test_batch_tiny_and_ragged_instances(precision):
+    # Degenerate and ragged members: N = 1 (no couplings: q moves with p
+    # only), N = 2, N one past a tile edge, and three replicas (R padded to
+    # 64).  Each equals its standalone run bit for bit, and the FP32 batch
+    # follows the oracle.
+    import torch
+    si = ensure_built()
+    announce(f"batch of tiny and ragged instances ({precision})")
+    specs = [(1, "pm1"), (2, "gauss"), (65, "pm1"), (129, "gauss"), (3, "pm1")]
+    r, S, steps = 3, 60, 40
+    b, Js, xs = _batch(specs, S, r=r, precision=precision)
+    b.run(steps)
+    xb, pb, t = b.state()
+    eb = b.energy(exact=False)
+    torch.cuda.synchronize()
+    assert t == steps
+    dt, zeta = oracle_schedules(S)
+    for i, (n, kind) in enumerate(specs):
+        form, tile = ("fp32", BATCH_TILE) if precision == "fp32" else FORM_TILE[kind]
+        m = si.SpringIsing(to_dev(Js[i]), to_dev(xs[i]), total_steps=S, precision=form, tile=tile)
+        m.run(steps)
+        x, p, _ = m.state()
+        e = m.energy(exact=False)
+        torch.cuda.synchronize()
+        assert np.array_equal(x.cpu().numpy(), xb[i].cpu().numpy()), (i, n, kind)
+        assert np.array_equal(p.cpu().numpy(), pb[i].cpu().numpy()), (i, n, kind)
+        assert np.array_equal(e.cpu().numpy(), eb[i].cpu().numpy()), (i, n, kind)
+        m.close()
+        if precision == "fp32":
+            ref = oracle.run(Js[i].astype(np.float64), xs[i].T.astype(np.float64), None, dt, zeta,
+                             qmax=QMAX, n_steps=steps)
+            assert rel_err(xb[i].cpu().numpy(), ref["Q"]) <= 1e-5, (i, n, kind)
+            assert rel_err(pb[i].cpu().numpy(), ref["P"]) <= 1e-5, (i, n, kind)
+    b.close()
+
+
 def test_bf16_batch_one_step_bound():
     # One step from a random state: every instance within the element-wise
     # bound that BF16 positions (and the hi + lo residual of J) allow.
