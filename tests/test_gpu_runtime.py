@@ -1,4 +1,4 @@
-"""Runtime features: HIP-graph replay of run() and the autotuner."""
+"""Runtime features: HIP-graph replay of run(), the autotuner, kernel naming."""
 import numpy as np
 import pytest
 
@@ -139,3 +139,42 @@ def test_c_program_runs(tmp_path):
     announce("  " + r.stdout.strip())
     assert r.returncode == 0 and "match" in r.stdout, r.stdout + r.stderr
 
+
+
+def test_kernel_names_match_tile_tables_and_traffic_keys():
+    # Every tile id the library accepts reports the kernel name that its
+    # tile table spells out, and every counter-measured traffic entry of the
+    # benchmark names a kernel the library runs for that form.
+    import importlib.util
+    import os
+    import re
+
+    si = ensure_built()
+    announce("kernel names of every tile id, against the tile tables and the traffic keys")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    spec = importlib.util.spec_from_file_location("bench_names", os.path.join(root, "bench.py"))
+    bench = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(bench)
+    n, r = 256, 128
+    J = to_dev(instances.make_pm1(n, 5))
+    x0 = to_dev(instances.make_x0(n, r, 5))
+    seen = {}
+    for prec in ("fp32", "bf16x_fp8j", "bf16x_bf16j", "bf16x_hiloj", "bf16x3_exactj"):
+        names = set()
+        for tile in range(1, 64):
+            try:
+                m = si.SpringIsing(J, x0, total_steps=2, precision=prec, tile=tile)
+            except si.SpringIsingError as e:
+                assert e.status == si.SI_ERR_INVALID, (prec, tile, e)
+                continue
+            name = m.info()["kernel_name"]
+            assert m.info()["tile"] == tile
+            m.close()
+            pat = r"step_f32_\d+x\d+_w\dx\d_mfma\d+_k\d+_s\d_a\d" if prec == "fp32" else \
+                r"step_bf16_\d+x\d+_w\dx\d_k\d+_s\d"
+            assert re.fullmatch(pat, name), (prec, tile, name)
+            names.add(name)
+        assert names, prec
+        seen[prec] = names
+    for (kernel, form, _, _), _ in bench.MEASURED_TRAFFIC_BYTES.items():
+        assert kernel in seen[form], (kernel, form)
