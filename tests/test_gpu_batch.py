@@ -206,20 +206,23 @@ def test_batch_tiny_and_ragged_instances(precision):
     # Degenerate and ragged members: N = 1 (no couplings: q moves with p
     # only), N = 2, N one past a tile edge, and three replicas (R padded to
     # 64).  Each equals its standalone run bit for bit, and the FP32 batch
-    # follows the oracle.
+    # follows the oracle.  An odd step count leaves the state in the second
+    # ping-pong buffer, where the spins and energies are then read.
     import torch
     si = ensure_built()
     announce(f"batch of tiny and ragged instances ({precision})")
     specs = [(1, "pm1"), (2, "gauss"), (65, "pm1"), (129, "gauss"), (3, "pm1")]
-    r, S, steps = 3, 60, 40
+    r, S, steps = 3, 60, 41
     b, Js, xs = _batch(specs, S, r=r, precision=precision)
     b.run(steps)
     xb, pb, t = b.state()
     eb = b.energy(exact=False)
+    sb = b.spins()
     torch.cuda.synchronize()
     assert t == steps
     dt, zeta = oracle_schedules(S)
     for i, (n, kind) in enumerate(specs):
+        np.testing.assert_array_equal(sb[i].cpu().numpy().T, oracle.spins(xb[i].cpu().numpy().T))
         form, tile = ("fp32", BATCH_TILE) if precision == "fp32" else FORM_TILE[kind]
         m = si.SpringIsing(to_dev(Js[i]), to_dev(xs[i]), total_steps=S, precision=form, tile=tile)
         m.run(steps)
