@@ -151,12 +151,15 @@ si_status spring_ising_init(si_ctx **out, int32_t n, int32_t r, const float *J,
 
 /* Batched form: n_inst independent instances of uneven size stepped together
  * (one grouped launch per step covers every instance), sharing r, the
- * parameters and the schedules.
+ * parameters and the schedules.  The paper runs many independent tests at
+ * once as the pixels of one feature map (Fig. 3; Methods, hardware
+ * implementation); here the independent problems may also differ in N.
  *   n : host, n_inst sizes (1 .. 65536).
  *   J : host array of n_inst device pointers, instance i an n[i]*n[i]
  *       symmetric zero-diagonal matrix.
- *   x0: host array of n_inst device pointers, instance i r*n[i] floats;
- *       initial momenta are 0.
+ *   x0: host array of n_inst device pointers, instance i r*n[i] floats.
+ *   p0: host array of n_inst device pointers (instance i r*n[i] floats, or
+ *       NULL for zero momenta of that instance), or NULL: all momenta 0.
  * Precisions: FP32 (128x64 tiles, instances padded to 128), or the BF16 forms
  * BF16X_FP8J (every J exact in FP8), BF16X_HILOJ and BF16X_MIXEDJ (FP8 J
  * where exact, hi + lo BF16 J otherwise), on 128x64 tiles with instances
@@ -170,13 +173,20 @@ si_status spring_ising_init(si_ctx **out, int32_t n, int32_t r, const float *J,
  * relaxed_energy_grad are not available for a batch.  Synchronises once. */
 si_status spring_ising_init_batch(si_ctx **out, int32_t n_inst, const int32_t *n, int32_t r,
                                   const float *const *J, const float *const *x0,
-                                  const si_params *prm, void *hip_stream);
+                                  const float *const *p0, const si_params *prm,
+                                  void *hip_stream);
 
-/* Replace the per-step schedules (device, total_steps floats each).
- * Delta_n must be > 0; values are not checked on the host. */
+/* Replace the per-step schedules (device, total_steps floats each): the time
+ * step Delta_n and the dynamic-equilibrium weight zeta_n of Eq. (8).  The
+ * paper varies zeta with the iteration count (Methods: zeta(t_step), a
+ * piecewise-constant function) and compares fixed and staircase strategies
+ * in Fig. 5; any such schedule is given here as explicit per-step values.
+ * Delta_n must be > 0; values are not checked on the host.  The arrays are
+ * copied on the context's stream. */
 si_status spring_ising_set_schedule(si_ctx *ctx, const float *dt, const float *zeta);
 
-/* Copy the per-step schedules out (device, total_steps floats each). */
+/* Copy the per-step schedules Delta_n, zeta_n of Eq. (8) out (device,
+ * total_steps floats each; either may be NULL). */
 si_status spring_ising_get_schedule(si_ctx *ctx, float *dt, float *zeta);
 
 /* Set an external field h (device, n floats; Eq. 1).  It adds zeta_n h_i to
@@ -266,12 +276,17 @@ si_status spring_ising_get_best(si_ctx *ctx, double *best_e, int8_t *best_s);
  * FP32 products, compensated FP32 sums. */
 si_status spring_ising_hamiltonian(si_ctx *ctx, double *H);
 
-/* Copy the state out: x, p device r*n floats (either may be NULL); *t (host,
- * may be NULL) receives the step index. */
+/* Copy the state out: the positions q (x) and momenta p of Eq. (8) after
+ * t steps, device r*n floats each (replica-major; either may be NULL), and
+ * *t (host, may be NULL) the step index.  On a batch the instances are
+ * concatenated as described at init_batch. */
 si_status spring_ising_get_state(si_ctx *ctx, float *x, float *p, int32_t *t);
 
-/* Overwrite the state: x, p device r*n floats (p may be NULL for zeros),
- * 0 <= t <= total_steps.  Resuming from a saved state is bit-identical. */
+/* Overwrite the state (q, p) of Eq. (8) and the step index: x, p device
+ * r*n floats (p may be NULL for zeros), 0 <= t <= total_steps, so that the
+ * next step uses Delta_t, zeta_t.  Resuming from a state saved with
+ * get_state is bit-identical to an uninterrupted run.  Resets the best-state
+ * record of update_best. */
 si_status spring_ising_set_state(si_ctx *ctx, const float *x, const float *p, int32_t t);
 
 /* Gradient of the relaxed end-energy with respect to the step schedules
@@ -300,6 +315,18 @@ si_status spring_ising_destroy(si_ctx *ctx);
 
 /* Message of the last failed call on this thread ("" if none). */
 const char *spring_ising_last_error(void);
+
+/* Build id of this library: 16 hex digits of a hash over the sources and
+ * compiler flags it was built from (static string). */
+const char *spring_ising_build_id(void);
+
+/* Test hook for callers' error handling: the n-th HIP call that the context
+ * checks after this call (n >= 1) reports a failure although the call itself
+ * succeeded, which poisons the context exactly as a real HIP failure does
+ * (that call returns SI_ERR_HIP, every later call other than destroy
+ * SI_ERR_STATE).  No device operation is altered.  n = 0 cancels a pending
+ * injection; SI_ERR_INVALID if n < 0. */
+si_status spring_ising_debug_inject_hip_error(si_ctx *ctx, int32_t n);
 
 #ifdef __cplusplus
 }

@@ -47,6 +47,7 @@ __device__ __forceinline__ int lds_swz(int r) {
 struct TileShape {
   int32_t bm, bn;
   const char *name;
+  int32_t bk;  // slab depth: the padded contraction length must be a multiple
 };
 TileShape tile_shape(int32_t tile);
 

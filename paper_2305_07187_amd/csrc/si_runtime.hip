@@ -93,6 +93,9 @@ struct si_ctx {
   int32_t hflags[8] = {0};
   int32_t t = 0;
   bool poisoned = false;
+  int32_t inject_countdown = 0;  // test hook: > 0 fails the n-th checked HIP call
+  uint16_t *tune_qb = nullptr;    // autotune: saved BF16 planes of q
+  hipEvent_t tune_ev[2] = {nullptr, nullptr};
   int64_t bytes = 0;
   std::vector<void *> allocs;
   std::vector<float> host_dt, host_zeta;  // kept alive for the async upload
@@ -172,14 +175,23 @@ struct si_ctx {
   }
   ~si_ctx() {
     drop_graphs();
+    for (hipEvent_t e : tune_ev)
+      if (e) (void)hipEventDestroy(e);
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
     for (void *a : allocs) (void)hipFree(a);
   }
 };
 
+// Every HIP call of a context goes through this check: a failure poisons
+// the context.  A test hook (spring_ising_debug_inject_hip_error) can make
+// the n-th checked call after it report a failure although the call itself
+// succeeded, so that the poisoning path runs without any device fault.
 #define SI_HIP(ctx, expr)                                                              \
   do {                                                                                 \
     hipError_t _e = (expr);                                                            \
+    if ((ctx) && (ctx)->inject_countdown > 0 && --(ctx)->inject_countdown == 0 &&      \
+        _e == hipSuccess)                                                              \
+      _e = hipErrorUnknown;                                                            \
     if (_e != hipSuccess) {                                                            \
       if (ctx) (ctx)->poisoned = true;                                                 \
       return fail(_e == hipErrorOutOfMemory ? SI_ERR_OOM : SI_ERR_HIP, "%s: %s (%s)",  \
@@ -336,9 +348,26 @@ static int32_t choose_tile(int32_t n, int32_t r, int num_cus) {
   return best;
 }
 
+// Hash of the sources and build flags this library was compiled from, set
+// by the build script; the marker prefix lets a loader read it from the
+// file before loading it.
+#ifndef SI_BUILD_ID
+#define SI_BUILD_ID "unstamped"
+#endif
+static const char k_build_id[] = "SI_BUILD_ID:" SI_BUILD_ID;
+
 extern "C" {
 
 const char *spring_ising_last_error(void) { return g_last_error.c_str(); }
+
+const char *spring_ising_build_id(void) { return k_build_id + 12; }
+
+si_status spring_ising_debug_inject_hip_error(si_ctx *c, int32_t n) {
+  SI_USABLE(c);
+  if (n < 0) return fail(SI_ERR_INVALID, "debug_inject_hip_error: n=%d < 0", n);
+  c->inject_countdown = n;
+  return SI_OK;
+}
 
 si_status spring_ising_default_params(si_params *prm, int32_t total_steps) {
   if (!prm) return fail(SI_ERR_INVALID, "default_params: null");
@@ -473,7 +502,8 @@ si_status spring_ising_init(si_ctx **out, int32_t n, int32_t r, const float *J, 
 
 si_status spring_ising_init_batch(si_ctx **out, int32_t n_inst, const int32_t *n, int32_t r,
                                   const float *const *J, const float *const *x0,
-                                  const si_params *prm, void *hip_stream) {
+                                  const float *const *p0, const si_params *prm,
+                                  void *hip_stream) {
   if (!out) return fail(SI_ERR_INVALID, "init_batch: out is null");
   *out = nullptr;
   if (n_inst < 1 || r < 1 || !n || !J || !x0)
@@ -487,8 +517,10 @@ si_status spring_ising_init_batch(si_ctx **out, int32_t n_inst, const int32_t *n
   const bool lowp = prm->precision != SI_PREC_FP32;
   for (int32_t i = 0; i < n_inst; ++i) {
     if (n[i] < 1 || n[i] > 65536) return fail(SI_ERR_INVALID, "init_batch: n[%d]=%d", i, n[i]);
-    if (!is_device_ptr(J[i]) || !is_device_ptr(x0[i]))
-      return fail(SI_ERR_INVALID, "init_batch: J[%d], x0[%d] must be device pointers", i, i);
+    if (!is_device_ptr(J[i]) || !is_device_ptr(x0[i]) ||
+        (p0 && p0[i] && !is_device_ptr(p0[i])))
+      return fail(SI_ERR_INVALID, "init_batch: J[%d], x0[%d], p0[%d] must be device pointers", i,
+                  i, i);
   }
   si_ctx *c = new (std::nothrow) si_ctx();
   if (!c) return fail(SI_ERR_OOM, "init_batch: host allocation failed");
@@ -603,7 +635,8 @@ si_status spring_ising_init_batch(si_ctx **out, int32_t n_inst, const int32_t *n
     so += (int64_t)c->r_pad * c->b_npad[i];
     BINIT_HIP(launch_pack_matrix(J[i], n[i], c->b_J[i], c->b_J8[i], c->b_npad[i], c->stream));
     BINIT_HIP(launch_pack_state(x0[i], n[i], r, c->b_q[0][i], c->b_npad[i], c->r_pad, c->stream));
-    BINIT_HIP(launch_pack_state(nullptr, n[i], r, c->b_p[0][i], c->b_npad[i], c->r_pad, c->stream));
+    BINIT_HIP(launch_pack_state(p0 ? p0[i] : nullptr, n[i], r, c->b_p[0][i], c->b_npad[i],
+                                c->r_pad, c->stream));
     c->b_desc_host[i] = BatchDesc{c->b_J[i], c->b_q[0][i], c->b_q[1][i], c->b_p[0][i], c->b_p[1][i],
                                   c->b_npad[i], n[i]};
     if (lowp) {
@@ -711,6 +744,9 @@ si_status spring_ising_get_schedule(si_ctx *c, float *dt, float *zeta) {
 
 si_status spring_ising_set_field(si_ctx *c, const float *h) {
   SI_USABLE(c);
+  // captured launch sequences hold the field pointer (or its absence) in
+  // their kernel arguments, so none of them may be replayed after a change
+  c->drop_graphs();
   if (!h) {
     c->has_field = false;
     return SI_OK;
@@ -1088,9 +1124,22 @@ si_status spring_ising_set_graph(si_ctx *c, int32_t min_steps) {
   return SI_OK;
 }
 
+// Whether the step kernel of `tile` accepts this context's padded shape:
+// the checks its launcher makes (tile divides the padded rows and replicas,
+// slab depth divides the contraction, the ring fits the LDS), decided on the
+// host so that no candidate is rejected by a launch.
+static bool tile_launchable(const si_ctx *c, int32_t tile) {
+  if (c->qplanes && !tile_valid_bf16(tile, c->prm.precision)) return false;
+  const TileShape ts = shape_of(c->prm.precision, tile);
+  if (ts.bm <= 0 || ts.bn <= 0 || ts.bk <= 0) return false;
+  return c->n_pad % ts.bm == 0 && c->r_pad % ts.bn == 0 && c->n_pad % ts.bk == 0;
+}
+
 // Time every step kernel that can serve this context from its current state
 // and keep the fastest.  The state and step index are restored after each
-// candidate (one host synchronisation per candidate).
+// candidate (one host synchronisation per candidate).  Candidates are
+// filtered on the host before anything is launched; once a candidate has
+// been launched, any HIP failure poisons the context like everywhere else.
 si_status spring_ising_autotune(si_ctx *c, int32_t steps, int32_t *best_tile, float *best_us) {
   SI_USABLE(c);
   if (steps < 1) return fail(SI_ERR_INVALID, "autotune: steps < 1");
@@ -1098,43 +1147,47 @@ si_status spring_ising_autotune(si_ctx *c, int32_t steps, int32_t *best_tile, fl
   if ((int64_t)c->t + steps > c->prm.total_steps)
     return fail(SI_ERR_RANGE, "autotune: %d steps from t=%d exceed total_steps", steps, c->t);
   const int64_t NR = (int64_t)c->n_pad * c->r_pad;
-  float *save = nullptr;
-  uint16_t *save_b = nullptr;
+  // saved state: q and p in the adjoint's segment buffer, the BF16 planes of
+  // q in a buffer of their own; both kept for later calls
   if (!c->adj_seg || c->adj_seg_cap < 2 * NR) {
     SI_HIP(c, c->alloc(&c->adj_seg, 2 * NR));
     SI_HIP(c, c->alloc(&c->adj_mask, NR));
     c->adj_seg_cap = 2 * NR;
   }
-  save = c->adj_seg;
-  if (c->qplanes) SI_HIP(c, c->alloc(&save_b, NR * c->qplanes));
+  float *save = c->adj_seg;
+  if (c->qplanes && !c->tune_qb) SI_HIP(c, c->alloc(&c->tune_qb, NR * c->qplanes));
+  uint16_t *save_b = c->qplanes ? c->tune_qb : nullptr;
   const int32_t t0 = c->t, cur0 = c->cur, tile0 = c->tile;
   SI_HIP(c, hipMemcpyAsync(save, c->q[cur0], NR * 4, hipMemcpyDeviceToDevice, c->stream));
   SI_HIP(c, hipMemcpyAsync(save + NR, c->p[cur0], NR * 4, hipMemcpyDeviceToDevice, c->stream));
   if (save_b)
     SI_HIP(c, hipMemcpyAsync(save_b, c->qb[cur0], NR * 2 * c->qplanes, hipMemcpyDeviceToDevice,
                              c->stream));
-  hipEvent_t e0, e1;
-  SI_HIP(c, hipEventCreate(&e0));
-  SI_HIP(c, hipEventCreate(&e1));
+  if (!c->tune_ev[0]) {
+    SI_HIP(c, hipEventCreate(&c->tune_ev[0]));
+    SI_HIP(c, hipEventCreate(&c->tune_ev[1]));
+  }
+  hipEvent_t e0 = c->tune_ev[0], e1 = c->tune_ev[1];
   const bool lowp = c->qplanes != 0;
   const int32_t last = lowp ? TILE_BF16_LAST : TILE_F32_LAST;
+  const int32_t timed = steps - 1 > 0 ? steps - 1 : 1;
   int32_t best = tile0;
   float best_t = 1e30f;
   for (int32_t tile = 1; tile <= last; ++tile) {
-    if (lowp && !tile_valid_bf16(tile, c->prm.precision)) continue;
-    const TileShape ts = shape_of(c->prm.precision, tile);
-    if (c->n_pad % ts.bm || c->r_pad % ts.bn) continue;
+    if (!tile_launchable(c, tile)) continue;
     c->tile = tile;
+    // the split contraction's workspace (a candidate whose workspace cannot
+    // be allocated is skipped: nothing has been launched for it)
     if (ensure_split_ws(c) != hipSuccess) {
       (void)hipGetLastError();
       continue;
     }
     si_status st = do_steps(c, 1);  // warm-up (also loads the code object)
-    if (st == SI_OK) {
-      SI_HIP(c, hipEventRecord(e0, c->stream));
-      st = do_steps(c, steps - 1 > 0 ? steps - 1 : 1);
-      SI_HIP(c, hipEventRecord(e1, c->stream));
-    }
+    if (st != SI_OK) return st;
+    SI_HIP(c, hipEventRecord(e0, c->stream));
+    st = do_steps(c, timed);
+    if (st != SI_OK) return st;
+    SI_HIP(c, hipEventRecord(e1, c->stream));
     // restore the state for the next candidate
     SI_HIP(c, hipMemcpyAsync(c->q[cur0], save, NR * 4, hipMemcpyDeviceToDevice, c->stream));
     SI_HIP(c, hipMemcpyAsync(c->p[cur0], save + NR, NR * 4, hipMemcpyDeviceToDevice, c->stream));
@@ -1143,23 +1196,17 @@ si_status spring_ising_autotune(si_ctx *c, int32_t steps, int32_t *best_tile, fl
                                c->stream));
     c->t = t0;
     c->cur = cur0;
-    if (st != SI_OK) {
-      c->poisoned = false;  // a candidate the device cannot launch is skipped
-      (void)hipGetLastError();
-      continue;
-    }
     SI_HIP(c, hipEventSynchronize(e1));
     float ms = 0.f;
     SI_HIP(c, hipEventElapsedTime(&ms, e0, e1));
-    const float us = 1000.f * ms / (float)(steps - 1 > 0 ? steps - 1 : 1);
+    const float us = 1000.f * ms / (float)timed;
     if (us < best_t) {
       best_t = us;
       best = tile;
     }
   }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
   c->tile = best;
+  SI_HIP(c, ensure_split_ws(c));
   c->drop_graphs();
   if (best_tile) *best_tile = best;
   if (best_us) *best_us = best_t;

@@ -601,10 +601,10 @@ TileShape tile_shape_bf16(int32_t tile) {
   switch (tile) {
 #define SI_SHAPE(id, bm, bn, wm, wn, bk, st) \
   case id:                                   \
-    return {bm, bn, "step_bf16_" #bm "x" #bn "_w" #wm "x" #wn "_k" #bk "_s" #st};
+    return {bm, bn, "step_bf16_" #bm "x" #bn "_w" #wm "x" #wn "_k" #bk "_s" #st, bk};
     SI_BF16_TILES(SI_SHAPE)
 #undef SI_SHAPE
-    default: return {0, 0, "invalid"};
+    default: return {0, 0, "invalid", 0};
   }
 }
 

@@ -235,10 +235,10 @@ TileShape tile_shape(int32_t tile) {
 #define SI_SHAPE(id, bm, bn, wm, wn, mb, bk, st, ks) \
   case id:                                           \
     return {bm, bn,                                  \
-            "step_f32_" #bm "x" #bn "_w" #wm "x" #wn "_mfma" #mb "_k" #bk "_s" #st "_a" #ks};
+            "step_f32_" #bm "x" #bn "_w" #wm "x" #wn "_mfma" #mb "_k" #bk "_s" #st "_a" #ks, bk};
     SI_F32_TILES(SI_SHAPE)
 #undef SI_SHAPE
-    default: return {0, 0, "invalid"};
+    default: return {0, 0, "invalid", 0};
   }
 }
 

@@ -96,8 +96,9 @@ _SIGNATURES = {
     "spring_ising_get_best": [_P, _P, _P],
     "spring_ising_hamiltonian": [_P, _P],
     "spring_ising_autotune": [_P, _I, ctypes.POINTER(_I), ctypes.POINTER(ctypes.c_float)],
-    "spring_ising_init_batch": [ctypes.POINTER(_P), _I, _P, _I, _P, _P,
+    "spring_ising_init_batch": [ctypes.POINTER(_P), _I, _P, _I, _P, _P, _P,
                                 ctypes.POINTER(si_params), _P],
+    "spring_ising_debug_inject_hip_error": [_P, _I],
     "spring_ising_destroy": [_P],
 }
 
@@ -110,6 +111,9 @@ def load_library(path: str = LIB_PATH):
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is missing: build it with "
                            "`python -m paper_2305_07187_amd.build` (no fallback exists)")
+    # refuse a library built from other sources than those in the tree
+    from . import build as _build
+    expected = _build.check_fresh(path)
     # torch carries its own copy of the HIP runtime; load it first so that
     # the library binds to that copy and recognises torch's device pointers
     # (a second runtime in the process would not know them)
@@ -121,12 +125,26 @@ def load_library(path: str = LIB_PATH):
         fn.restype = ctypes.c_int
     lib.spring_ising_last_error.argtypes = []
     lib.spring_ising_last_error.restype = ctypes.c_char_p
+    lib.spring_ising_build_id.argtypes = []
+    lib.spring_ising_build_id.restype = ctypes.c_char_p
+    loaded = lib.spring_ising_build_id().decode()
+    if loaded != expected:
+        raise _build.StaleLibraryError(f"loaded library reports build id {loaded}, "
+                                       f"file and tree {expected}")
     _lib = lib
     return lib
 
 
 def last_error() -> str:
     return load_library().spring_ising_last_error().decode()
+
+
+def spring_ising_build_id() -> str:
+    return load_library().spring_ising_build_id().decode()
+
+
+def spring_ising_debug_inject_hip_error(ctx, n):
+    _check(load_library().spring_ising_debug_inject_hip_error(ctx, int(n)))
 
 
 def _check(status: int):
@@ -179,13 +197,19 @@ def spring_ising_init(n, r, J, x0, p0=None, params=None, stream=None):
     return ctx
 
 
-def spring_ising_init_batch(ns, r, Js, x0s, params, stream=None):
-    """Js, x0s: lists of CUDA float32 tensors (n_i*n_i and r*n_i elements)."""
+def spring_ising_init_batch(ns, r, Js, x0s, params, stream=None, p0s=None):
+    """Js, x0s: lists of CUDA float32 tensors (n_i*n_i and r*n_i elements);
+    p0s: None (zero momenta) or a list of such tensors or None per instance."""
     import torch
     lib = load_library()
     k = len(ns)
-    if not (len(Js) == len(x0s) == k):
-        raise ValueError("one J and one x0 per instance")
+    if not (len(Js) == len(x0s) == k) or (p0s is not None and len(p0s) != k):
+        raise ValueError("one J, one x0 (and one p0 entry if given) per instance")
+    p_arr = None
+    if p0s is not None:
+        p_arr = (ctypes.c_void_p * k)(*[None if p0s[i] is None else
+                                        _ptr(p0s[i], torch.float32, ns[i] * r, "p0").value
+                                        for i in range(k)])
     n_arr = (ctypes.c_int32 * k)(*[int(v) for v in ns])
     j_arr = (ctypes.c_void_p * k)(*[_ptr(Js[i], torch.float32, ns[i] * ns[i], "J").value
                                     for i in range(k)])
@@ -194,7 +218,9 @@ def spring_ising_init_batch(ns, r, Js, x0s, params, stream=None):
     ctx = ctypes.c_void_p()
     st = lib.spring_ising_init_batch(ctypes.byref(ctx), k, ctypes.cast(n_arr, ctypes.c_void_p),
                                      int(r), ctypes.cast(j_arr, ctypes.c_void_p),
-                                     ctypes.cast(x_arr, ctypes.c_void_p), ctypes.byref(params),
+                                     ctypes.cast(x_arr, ctypes.c_void_p),
+                                     None if p_arr is None else ctypes.cast(p_arr, ctypes.c_void_p),
+                                     ctypes.byref(params),
                                      stream if stream is not None else _stream())
     _check(st)
     return ctx
@@ -307,11 +333,12 @@ def spring_ising_destroy(ctx):
 class SpringIsingBatch:
     """Owns one batched context: instances of uneven size stepped together.
 
-    Js: list of [N_i, N_i] float32 CUDA tensors; x0s: list of [R, N_i].
+    Js: list of [N_i, N_i] float32 CUDA tensors; x0s: list of [R, N_i];
+    p0s: None (zero momenta) or a list of [R, N_i] tensors or None.
     Outputs are lists per instance.
     """
 
-    def __init__(self, Js, x0s, total_steps=1000, **overrides):
+    def __init__(self, Js, x0s, total_steps=1000, p0s=None, **overrides):
         import torch
         self.ns = [int(J.shape[0]) for J in Js]
         self.r = int(x0s[0].shape[0])
@@ -322,8 +349,9 @@ class SpringIsingBatch:
             setattr(prm, key, val)
         self.total_steps = int(prm.total_steps)
         self.device = Js[0].device
-        keep = ([J.contiguous() for J in Js], [x.contiguous() for x in x0s])
-        self.ctx = spring_ising_init_batch(self.ns, self.r, keep[0], keep[1], prm)
+        keep = ([J.contiguous() for J in Js], [x.contiguous() for x in x0s],
+                None if p0s is None else [None if p is None else p.contiguous() for p in p0s])
+        self.ctx = spring_ising_init_batch(self.ns, self.r, keep[0], keep[1], prm, p0s=keep[2])
         torch.cuda.current_stream().synchronize()
         self.offsets = [0]
         for n in self.ns:

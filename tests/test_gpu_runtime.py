@@ -178,3 +178,120 @@ def test_kernel_names_match_tile_tables_and_traffic_keys():
         seen[prec] = names
     for (kernel, form, _, _), _ in bench.MEASURED_TRAFFIC_BYTES.items():
         assert kernel in seen[form], (kernel, form)
+
+
+def test_set_field_invalidates_captured_graphs():
+    # A captured run(n) holds the field pointer in its kernel arguments:
+    # changing the field must drop the graphs, so that a replay after a
+    # rewind uses the new field exactly like direct launches do.
+    import torch
+    si = ensure_built()
+    announce("set_field after a graph capture: graphs dropped")
+    n, r, S = 200, 64, 120
+    J = to_dev(instances.make_pm1(n, 7))
+    x0 = to_dev(instances.make_x0(n, r, 7))
+    h = to_dev(np.linspace(-1.0, 1.0, n).astype(np.float32))
+
+    def sequence(graph):
+        m = si.SpringIsing(J, x0, total_steps=S)
+        if graph:
+            m.set_graph(10)
+        m.run(60)                     # captured (graph on) with no field
+        m.set_field(h)
+        m.set_state(x0, None, 0)
+        m.run(60)                     # same key (t0 = 0, 60 steps): must see the field
+        x1, p1, _ = m.state()
+        m.set_field(None)
+        m.set_state(x0, None, 0)
+        m.run(60)                     # and again without it
+        x2, p2, _ = m.state()
+        torch.cuda.synchronize()
+        m.close()
+        return x1, p1, x2, p2
+
+    direct = sequence(False)
+    graphed = sequence(True)
+    for a, b in zip(direct, graphed):
+        assert torch.equal(a, b)
+    # the field made a difference (the test would be void otherwise)
+    assert not torch.equal(direct[0], direct[2])
+
+
+@pytest.mark.parametrize("after", [1, 3])
+def test_injected_hip_failure_poisons_context(after):
+    # The test hook makes the n-th checked HIP call report a failure
+    # although the call succeeded: that call returns SI_ERR_HIP, every later
+    # call other than destroy SI_ERR_STATE.  No device operation is altered.
+    import torch
+    si = ensure_built()
+    announce(f"injected HIP failure after {after} checked calls")
+    n, r = 64, 8
+    m = si.SpringIsing(to_dev(instances.make_pm1(n, 1)), to_dev(instances.make_x0(n, r, 1)),
+                       total_steps=100)
+    with pytest.raises(si.SpringIsingError) as e:
+        si.spring_ising_debug_inject_hip_error(m.ctx, -1)
+    assert e.value.status == si.SI_ERR_INVALID
+    si.spring_ising_debug_inject_hip_error(m.ctx, 0)   # cancel: nothing pending
+    m.run(5)
+    si.spring_ising_debug_inject_hip_error(m.ctx, after)
+    with pytest.raises(si.SpringIsingError) as e:
+        m.run(10)                     # ten step launches: the after-th reports failure
+    assert e.value.status == si.SI_ERR_HIP, e.value
+    for call in (lambda: m.run(1), lambda: m.energy(), lambda: m.state(),
+                 lambda: m.autotune(2), lambda: m.set_graph(5)):
+        with pytest.raises(si.SpringIsingError) as e:
+            call()
+        assert e.value.status == si.SI_ERR_STATE
+    torch.cuda.synchronize()
+    m.close()                         # destroy still works
+    # other contexts are unaffected
+    m2 = si.SpringIsing(to_dev(instances.make_pm1(n, 1)), to_dev(instances.make_x0(n, r, 1)),
+                        total_steps=10)
+    m2.run(10)
+    m2.energy()
+    torch.cuda.synchronize()
+    m2.close()
+
+
+def test_autotune_failure_after_launch_poisons_context():
+    # A failure after a candidate has been launched is not skipped: the
+    # autotuner returns SI_ERR_HIP and the context stays poisoned.
+    si = ensure_built()
+    announce("autotune: a failure after launch poisons the context")
+    n, r = 256, 128
+    m = si.SpringIsing(to_dev(instances.make_pm1(n, 3)), to_dev(instances.make_x0(n, r, 3)),
+                       total_steps=100)
+    si.spring_ising_debug_inject_hip_error(m.ctx, 12)
+    with pytest.raises(si.SpringIsingError) as e:
+        m.autotune(3)
+    assert e.value.status == si.SI_ERR_HIP
+    with pytest.raises(si.SpringIsingError) as e:
+        m.run(1)
+    assert e.value.status == si.SI_ERR_STATE
+    m.close()
+
+
+def test_batch_initial_momenta():
+    # init_batch takes per-instance initial momenta (NULL entries are zero):
+    # every instance equals its single-instance run from the same (x0, p0)
+    # on the tile whose contraction order the batch uses (FP32: tile 14).
+    import torch
+    si = ensure_built()
+    announce("batch with initial momenta vs single-instance runs")
+    specs = [(96, "pm1"), (200, "gauss"), (130, "pm1")]
+    r, S = 64, 40
+    Js = [to_dev(instances.make_J(n, k, 20 + i)) for i, (n, k) in enumerate(specs)]
+    xs = [to_dev(instances.make_x0(n, r, 20 + i)) for i, (n, k) in enumerate(specs)]
+    ps = [to_dev(0.5 * instances.make_x0(n, r, 40 + i)), None,
+          to_dev(-0.3 * instances.make_x0(n, r, 60))]
+    b = si.SpringIsingBatch(Js, xs, total_steps=S, p0s=ps)
+    b.run(S)
+    xb, pb, _ = b.state()
+    for i in range(len(specs)):
+        m = si.SpringIsing(Js[i], xs[i], ps[i], total_steps=S, tile=14)
+        m.run(S)
+        x, p, _ = m.state()
+        torch.cuda.synchronize()
+        assert torch.equal(x, xb[i]) and torch.equal(p, pb[i]), i
+        m.close()
+    b.close()
