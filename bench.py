@@ -36,6 +36,11 @@ import os
 import sys
 import time
 
+# The CPU baseline's BLAS uses every core of this process's share; set before
+# NumPy is first imported (an OMP_NUM_THREADS already set by the host wins).
+os.environ.setdefault("OMP_NUM_THREADS", str(len(os.sched_getaffinity(0))))
+os.environ.setdefault("OPENBLAS_NUM_THREADS", os.environ["OMP_NUM_THREADS"])
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
@@ -60,12 +65,41 @@ MEASURED_TRAFFIC_BYTES = {
 }
 
 
-def cpu_baseline(budget_s: float = 15.0):
-    """Time the FP64 oracle (as it stands) on a bounded sample of the same
-    workload on the host cores; extrapolate per iteration."""
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_steps(J, Q, P, iters, budget_s):
+    """FP64 oracle steps of the paper schedule until `iters` or the budget."""
     import numpy as np
 
     import oracle
+    dt = oracle.dt_schedule(iters)
+    zeta = oracle.zeta_schedule(iters, float(np.float32(0.04)), float(np.float32(0.5)))
+    qmax = float(np.float32(np.sqrt(2.0)))
+    t0 = time.perf_counter()
+    done = 0
+    while done < iters and time.perf_counter() - t0 < budget_s:
+        Q, P = oracle.step(J, Q, P, float(dt[done]), float(zeta[done]), qmax=qmax)
+        done += 1
+    return done, time.perf_counter() - t0
+
+
+def cpu_baseline(budget_s: float = 15.0, subset_budget_s: float = 6.0):
+    """Time the FP64 oracle (as it stands, J @ Q on the host BLAS) on a
+    bounded sample of the headline workload on the host cores and
+    extrapolate per iteration; also on the precision form's N = 8000
+    Gaussian configuration at R = 64 and on 16 sampled instances of the
+    batched configuration (R = 64)."""
+    import numpy as np
+
     from paper_2305_07187_amd import instances
     try:
         from threadpoolctl import threadpool_info
@@ -74,20 +108,43 @@ def cpu_baseline(budget_s: float = 15.0):
         cores = os.cpu_count()
     J = instances.make_pm1(N, 0).astype(np.float64)
     Q = instances.make_x0(N, R, 0).T.astype(np.float64)
-    P = np.zeros_like(Q)
-    dt = oracle.dt_schedule(ITERS)
-    zeta = oracle.zeta_schedule(ITERS, float(np.float32(0.04)), float(np.float32(0.5)))
-    qmax = float(np.float32(np.sqrt(2.0)))
-    t0 = time.perf_counter()
-    done = 0
-    while done < ITERS and time.perf_counter() - t0 < budget_s:
-        Q, P = oracle.step(J, Q, P, float(dt[done]), float(zeta[done]), qmax=qmax)
-        done += 1
-    el = time.perf_counter() - t0
-    return {"value": N * R * done / el, "unit": "spin-updates/s", "cores": int(cores),
-            "kind": "oracle",
-            "sample": f"first {done} of {ITERS} iterations at N={N}, R={R} (FP64 NumPy, "
-                      f"{el:.1f} s), extrapolated per iteration"}
+    done, el = _oracle_steps(J, Q, np.zeros_like(Q), ITERS, budget_s)
+    out = {"value": N * R * done / el, "unit": "spin-updates/s", "cores": int(cores),
+           "kind": "oracle",
+           "sample": f"first {done} of {ITERS} iterations at N={N}, R={R} (FP64 NumPy, "
+                     f"{el:.1f} s), extrapolated per iteration",
+           "cpu_model": _cpu_model(), "affinity_cpus": len(os.sched_getaffinity(0)),
+           "blas_threads_env": os.environ.get("OPENBLAS_NUM_THREADS")}
+    # precision form, Gaussian N = 8000, on an R = 64 subset of its R = 2048
+    n8, r8 = 8000, 64
+    # the same values as instances.make_gauss, drawn by the torch form of the
+    # generator on the device (the NumPy form takes about 15 s at this size)
+    import torch
+    gen_dev = torch.device("cuda:0") if torch.cuda.is_available() else torch.device("cpu")
+    J8 = instances.make_J_torch(n8, "gauss", 0, gen_dev).cpu().numpy().astype(np.float64)
+    Q8 = instances.make_x0(n8, r8, 0).T.astype(np.float64)
+    d8, e8 = _oracle_steps(J8, Q8, np.zeros_like(Q8), 5000, subset_budget_s)
+    del J8, Q8
+    # batched form: 16 of the 256 instances (every 16th of the recipe), R = 64
+    recipe = instances.make_batch(256, 0)[::16]
+    spins_done, el3, steps3 = 0, 0.0, 0
+    per = subset_budget_s / len(recipe)
+    for n_i, kind, seed in recipe:
+        Ji = instances.make_J(n_i, kind, seed).astype(np.float64)
+        Qi = instances.make_x0(n_i, 64, seed).T.astype(np.float64)
+        d, e = _oracle_steps(Ji, Qi, np.zeros_like(Qi), 3000, per)
+        spins_done += n_i * 64 * d
+        el3 += e
+        steps3 += d
+    out["subsets"] = {
+        "precision_gauss_n8000": {"value": n8 * r8 * d8 / e8, "unit": "spin-updates/s",
+                                  "sample": f"{d8} iterations at N={n8}, R={r8} of R=2048 "
+                                            f"(FP64 NumPy, {e8:.1f} s)"},
+        "batched_16_instances": {"value": spins_done / el3, "unit": "spin-updates/s",
+                                 "sample": f"{steps3} iterations over 16 of the 256 instances "
+                                           f"(N {min(r[0] for r in recipe)}..{max(r[0] for r in recipe)}), "
+                                           f"R=64 ({el3:.1f} s)"}}
+    return out
 
 
 def batched_form(si, steps=300, n_inst=256, r=64, sequential=True, time_to_target=True):
@@ -130,7 +187,8 @@ def batched_form(si, steps=300, n_inst=256, r=64, sequential=True, time_to_targe
     if time_to_target:
         ref_xs = [instances.make_x0_torch(n, r, seed ^ 0x5A5A5A5A, device=dev)
                   for n, kind, seed in recipe]
-        out["time_to_target"] = batched_time_to_target(si, Js, xs, ref_xs)
+        out["time_to_target"] = batched_time_to_target(si, Js, xs, ref_xs,
+                                                       sequential=sequential)
     if not sequential:
         return out
     seq = 0.0
@@ -150,14 +208,33 @@ def batched_form(si, steps=300, n_inst=256, r=64, sequential=True, time_to_targe
     return out
 
 
-def batched_time_to_target(si, Js, xs, ref_xs, steps=3000, every=100, rank=13):
+def _chunked_run(model, every, checks, stream):
+    """model.run(every) `checks` times with a HIP event after each chunk (the
+    in-run energy check closes every chunk); returns the event times in s
+    from the start."""
+    import torch
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(checks + 1)]
+    evs[0].record(stream)
+    for c in range(checks):
+        model.run(every)
+        evs[c + 1].record(stream)
+    torch.cuda.synchronize()
+    return [evs[0].elapsed_time(e) / 1000.0 for e in evs[1:]]
+
+
+def batched_time_to_target(si, Js, xs, ref_xs, steps=3000, every=100, rank=13,
+                           sequential=True):
     """Time to target energy of the batched forms over the batched workload's
     3000 steps.  Each instance's target is the `rank`-th best of its R final
     energies in a separate FP32 batch run from other initial states (ref_xs),
-    so that neither timed form is measured against its own final energies; a
-    form's time to target is the HIP-event time of the first check (every
-    `every` steps, energies of all instances on the stream) at which every
-    instance has a replica at or below its target."""
+    so that no timed form is measured against its own final energies.  The
+    energies of all instances are checked on the device every `every` steps
+    (si_params.energy_every, the check cost included); a batched form's time
+    to target is the HIP-event time of the first check at which every
+    instance has a replica at or below its target.  The sequential FP32
+    reference steps each instance alone as a single FP32 context with the
+    same checks until it reaches its target; its time to target is the sum of
+    those per-instance times (the instances solved one after another)."""
     import numpy as np
     import torch
 
@@ -170,31 +247,49 @@ def batched_time_to_target(si, Js, xs, ref_xs, steps=3000, every=100, rank=13):
     ref.run(steps)
     targets = np.sort(torch.stack(ref.energy(exact=False)).cpu().numpy(), axis=1)[:, rank - 1]
     ref.close()
-    recorded = {}
     for form in ("fp32", "bf16x_mixedj"):
-        b = si.SpringIsingBatch(Js, xs, total_steps=steps, precision=form)
+        b = si.SpringIsingBatch(Js, xs, total_steps=steps, precision=form, energy_every=every)
         b.run(every)  # warm-up
         b.set_state(xs, None, 0)
         torch.cuda.synchronize()
-        evs = [torch.cuda.Event(enable_timing=True) for _ in range(checks + 1)]
-        energies = []
-        evs[0].record(stream)
-        for c in range(checks):
-            b.run(every)
-            energies.append(b.energy(exact=False))
-            evs[c + 1].record(stream)
-        torch.cuda.synchronize()
-        times = [evs[0].elapsed_time(e) / 1000.0 for e in evs[1:]]
-        mins = np.stack([torch.stack(es).min(dim=1).values.cpu().numpy() for es in energies])
-        recorded[form] = (mins, times)
+        times = _chunked_run(b, every, checks, stream)
+        mins = b.energy_trace().min(dim=2).values.cpu().numpy()  # [checks, n_inst]
         b.close()
-    for form, (mins, times) in recorded.items():
         hit = np.nonzero((mins <= targets[None, :]).all(axis=1))[0]
         out[form] = {"ttt_s": float(times[hit[0]]) if len(hit) else None,
                      "ttt_step": int((hit[0] + 1) * every) if len(hit) else None,
                      "instances_at_target_at_end": int((mins[-1] <= targets).sum())}
     t32, t16 = out["fp32"]["ttt_s"], out["bf16x_mixedj"]["ttt_s"]
     out["bf16_speedup_vs_fp32"] = (t32 / t16) if (t32 and t16) else None
+    if sequential:
+        total, reached, block = 0.0, 0, 5
+        for i, (J, x) in enumerate(zip(Js, xs)):
+            m = si.SpringIsing(J, x, total_steps=steps, energy_every=every)
+            m.run(every)  # warm-up (code objects of this instance's tile)
+            m.set_state(x, None, 0)
+            torch.cuda.synchronize()
+            t_i, done = None, 0
+            while done < checks and t_i is None:
+                k = min(block, checks - done)
+                times = _chunked_run(m, every, k, stream)
+                mins = m.energy_trace()[done:done + k].min(dim=1).values.cpu().numpy()
+                h = np.nonzero(mins <= targets[i])[0]
+                if len(h):
+                    t_i = float(times[h[0]])
+                else:
+                    total += times[-1]
+                done += k
+            if t_i is not None:
+                total += t_i
+                reached += 1
+            m.close()
+        out["fp32_sequential"] = {"ttt_s": total, "instances_reaching_target": reached,
+                                  "note": "each instance alone (single FP32 context, its own "
+                                          "automatic tile), stopped at its first check at or "
+                                          "below its target; times summed"}
+        t_seq = total if reached == len(Js) else None
+        out["batched_fp32_speedup_vs_sequential"] = (t_seq / t32) if (t_seq and t32) else None
+        out["batched_bf16_speedup_vs_sequential"] = (t_seq / t16) if (t_seq and t16) else None
     return out
 
 
@@ -273,10 +368,10 @@ def differentiation_form(si, n=2000, r=64, steps=2000, ckpt=100, repeats=3):
 
 
 def timed_runs(model, x0, iters, steps, warmup, stream):
-    exact = bool(model.info()["j_integer"])
     """Full runs (reset, iters steps, energy); per-run HIP events bracket the
     step launches.  Returns (elapsed_s, per-launch us, last energies)."""
     import torch
+    exact = bool(model.info()["j_integer"])
 
     def one_run(ev=None):
         model.set_state(x0, None, 0)
@@ -303,22 +398,94 @@ def timed_runs(model, x0, iters, steps, warmup, stream):
     return elapsed, kernel_us, energies
 
 
-def run_with_checks(si, model, x0, iters, every, stream):
-    """One run with the exact energy of all replicas every `every` steps."""
-    import torch
+TTT_SEEDS = (0, 1, 2, 3, 4)
+TTT_TARGET_SEED = 5
+
+
+def time_to_target(si, J, n, r, iters, every, stream, runs_per_form):
+    """Time to target energy, BF16 forms against FP32, on the headline
+    instance.  Target: the 1 % quantile (10th best of 1024) of the final
+    energies of an FP32 run from initial positions of seed 5, so that no
+    timed run is measured against its own final energies.  Every form runs
+    the whole schedule from the initial positions of seeds 0-4 with the
+    energies of all replicas checked on the device every `every` steps
+    (si_params.energy_every; check cost included); its time to target for a
+    seed is the HIP-event time of the first check with a replica at or below
+    the target, and the form's figure is the median over the seeds.  Equal
+    final-energy distribution: a two-sample KS test of the pooled final
+    energies (R x 5 seeds) against FP32's, and the difference of the means in
+    standard errors.  TTS99 = t_run ln(0.01) / ln(1 - P_s), P_s the pooled
+    fraction of replicas ending at or below the target."""
+    import math
+
+    import numpy as np
+    from scipy.stats import ks_2samp
+
+    from paper_2305_07187_amd import instances
+    dev = J.device
     checks = iters // every
-    E = torch.empty(checks, model.r, dtype=torch.int32, device=x0.device)
-    evs = [torch.cuda.Event(enable_timing=True) for _ in range(checks + 1)]
-    model.set_state(x0, None, 0)
-    torch.cuda.synchronize()
-    evs[0].record(stream)
-    for c in range(checks):
-        model.run(every)
-        si.spring_ising_energy(model.ctx, E[c], None)
-        evs[c + 1].record(stream)
-    torch.cuda.synchronize()
-    times = [evs[0].elapsed_time(e) for e in evs[1:]]
-    return E.cpu().numpy(), times
+    mref = si.SpringIsing(J, instances.make_x0_torch(n, r, TTT_TARGET_SEED, device=dev),
+                          total_steps=iters, precision="fp32")
+    mref.run(iters)
+    e_ref = mref.energy(exact=bool(mref.info()["j_integer"])).cpu().numpy().astype(np.float64)
+    mref.close()
+    target = float(np.sort(e_ref)[max(0, int(0.01 * r) - 1)])
+    x0s = {sd: instances.make_x0_torch(n, r, sd, device=dev) for sd in TTT_SEEDS}
+    forms, finals = {}, {}
+    for name in ["fp32"] + FORMS:
+        # throughput of the form on full runs without in-run checks
+        plain = si.SpringIsing(J, x0s[0], total_steps=iters, precision=name)
+        el_tot, us, _ = timed_runs(plain, x0s[0], iters, runs_per_form, 1, stream)
+        plain.close()
+        m = si.SpringIsing(J, x0s[0], total_steps=iters, precision=name, energy_every=every)
+        m.run(every)  # warm-up
+        per_seed, pooled = [], []
+        for sd in TTT_SEEDS:
+            m.set_state(x0s[sd], None, 0)
+            times = _chunked_run(m, every, checks, stream)
+            tr = m.energy_trace().cpu().numpy()
+            hit = np.nonzero(tr.min(axis=1) <= target)[0]
+            per_seed.append({"seed": sd, "ttt_s": float(times[hit[0]]) if len(hit) else None,
+                             "ttt_step": int((hit[0] + 1) * every) if len(hit) else None,
+                             "run_s": float(times[-1])})
+            pooled.append(tr[-1])  # the last check is at the final step
+        kernel = m.info()["kernel_name"]
+        m.close()
+        fin = np.concatenate(pooled)
+        finals[name] = fin
+        ttts = sorted((p["ttt_s"] if p["ttt_s"] is not None else math.inf) for p in per_seed)
+        med = ttts[len(ttts) // 2]
+        p_s = float((fin <= target).mean())
+        t_run = float(np.median([p["run_s"] for p in per_seed]))
+        if p_s >= 0.99:
+            tts99 = t_run
+        elif p_s > 0:
+            tts99 = t_run * math.log(0.01) / math.log(1.0 - p_s)
+        else:
+            tts99 = None
+        forms[name] = {"kernel": kernel, "spin_updates_per_s": n * r * iters * runs_per_form / el_tot,
+                       "avg_launch_us": us,
+                       "ttt_median_s": med if math.isfinite(med) else None,
+                       "per_seed": per_seed, "run_with_checks_s": t_run,
+                       "p_success": p_s, "tts99_s": tts99,
+                       "mean_energy": float(fin.mean()), "best_energy": float(fin.min())}
+    t32 = forms["fp32"]["ttt_median_s"]
+    for name in FORMS:
+        f = forms[name]
+        f["ks_pvalue_vs_fp32"] = float(ks_2samp(finals[name], finals["fp32"]).pvalue)
+        a, b = finals[name], finals["fp32"]
+        f["mean_diff_in_se"] = float((a.mean() - b.mean()) /
+                                     math.sqrt(a.var() / len(a) + b.var() / len(b)))
+        f["equal_distribution"] = bool(f["ks_pvalue_vs_fp32"] >= 0.01 and
+                                       abs(f["mean_diff_in_se"]) <= 2.0)
+        tf = f["ttt_median_s"]
+        f["ttt_speedup_vs_fp32"] = (t32 / tf) if (t32 and tf) else None
+        f["tts99_speedup_vs_fp32"] = (forms["fp32"]["tts99_s"] / f["tts99_s"]
+                                      if (forms["fp32"]["tts99_s"] and f["tts99_s"]) else None)
+    return {"target_energy": target, "check_every": every, "seeds": list(TTT_SEEDS),
+            "target": f"1% quantile of the final energies of an FP32 run from initial "
+                      f"positions of seed {TTT_TARGET_SEED}",
+            "forms": forms}
 
 
 def main():
@@ -426,48 +593,8 @@ def main():
                                "best_energy": float(e1.min()), "mean_energy": float(e1.mean())}
 
     if fp32_line and not args.no_forms and iters % CHECK_EVERY == 0 and args.couplings == "pm1":
-        from scipy.stats import ks_2samp
-        # target: the 1% quantile (10th best) of the final energies of an
-        # FP32 run from other initial states, so that no timed run is
-        # measured against its own final energies
-        mref = si.SpringIsing(J, instances.make_x0_torch(n, r, 1, device=dev), total_steps=iters,
-                              precision="fp32")
-        mref.run(iters)
-        e_ref = mref.energy(exact=bool(mref.info()["j_integer"])).cpu().numpy().astype(np.float64)
-        mref.close()
-        target = float(np.sort(e_ref)[max(0, int(0.01 * r) - 1)])
-        forms = {}
-        for name in ["fp32"] + FORMS:
-            m = model if name == "fp32" else si.SpringIsing(J, x0, total_steps=iters,
-                                                              precision=name)
-            if name == "fp32":
-                el, us, en = elapsed / args.steps, kernel_us, e
-            else:
-                el_tot, us, en_t = timed_runs(m, x0, iters, args.steps, 1, stream)
-                el, en = el_tot / args.steps, en_t.cpu().numpy().astype(np.float64)
-            Ec, times = run_with_checks(si, m, x0, iters, CHECK_EVERY, stream)
-            hit = np.nonzero(Ec.min(axis=1) <= target)[0]
-            frac_at_end = float((en <= target).mean())
-            rec = {"spin_updates_per_s": n * r * iters / el, "avg_launch_us": us,
-                   "kernel": m.info()["kernel_name"],
-                   "ttt_s": float(times[hit[0]]) / 1000.0 if len(hit) else None,
-                   "ttt_step": int((hit[0] + 1) * CHECK_EVERY) if len(hit) else None,
-                   "mean_energy": float(en.mean()), "best_energy": float(en.min()),
-                   "frac_at_or_below_target": frac_at_end}
-            if name != "fp32":
-                rec["ks_pvalue_vs_fp32"] = float(ks_2samp(en, e).pvalue)
-                rec["mean_diff_in_se"] = float((en.mean() - e.mean()) /
-                                               np.sqrt(en.var() / r + e.var() / r))
-                m.close()
-            forms[name] = rec
-        t32 = forms["fp32"]["ttt_s"]
-        for name in FORMS:
-            tf = forms[name]["ttt_s"]
-            forms[name]["ttt_speedup_vs_fp32"] = (t32 / tf) if (t32 and tf) else None
-        out["time_to_target"] = {"target_energy": target, "check_every": CHECK_EVERY,
-                                 "target": "1% quantile of the final energies of an FP32 run "
-                                           "from other initial states",
-                                 "forms": forms}
+        out["time_to_target"] = time_to_target(si, J, n, r, iters, CHECK_EVERY, stream,
+                                               runs_per_form=max(1, min(args.steps, 5)))
     model.close()
     if fp32_line and not args.no_forms and (n, r, args.couplings) == (N, R, "pm1"):
         out["precision_full_configurations"] = precision_full_configurations(si)

@@ -109,6 +109,15 @@ typedef struct {
   int32_t precision;  /* si_precision */
   int32_t tile;       /* 0 = automatic kernel choice; otherwise a tile id
                          reported by spring_ising_info (tuning override) */
+  int32_t energy_every; /* E >= 0.  E > 0: in-run energy checks.  After every
+                         step that brings the step index t to a multiple of E,
+                         the Eq. (1) energies of all replicas' spins are
+                         written on the device to row t/E - 1 of the
+                         context's energy trace (total_steps / E rows) and
+                         update the best-state record (see update_best); the
+                         check is part of the step sequence, so it also runs
+                         inside captured HIP graphs.  The paper follows the
+                         energy over the iterations (Fig. 4).  0 = off. */
 } si_params;
 
 /* Read-only facts about a context (host struct). */
@@ -259,15 +268,30 @@ si_status spring_ising_spins(si_ctx *ctx, int8_t *s);
  * instances, then real ones), with the values of its single-instance call. */
 si_status spring_ising_energy(si_ctx *ctx, int32_t *e_int, double *e_real);
 
-/* In-run best state: evaluate the energy of the current spins (exactly for
- * integer J, else as the real energy) and keep, per replica, the lowest value
- * seen since init or the last set_state together with its spins. */
+/* Best state seen along the trajectory (the paper samples the spins of the
+ * final state, Methods; tracking the lowest energy met on the way, Fig. 4,
+ * keeps the best of them): evaluate the Eq. (1) energy of the current spins
+ * (exactly for integer J, else as the real energy) and keep, per replica,
+ * the lowest value seen since init or the last set_state together with its
+ * spins.  Also done by every in-run energy check (si_params.energy_every).
+ * On a batch, per instance and replica. */
 si_status spring_ising_update_best(si_ctx *ctx);
 
-/* Copy the recorded best energies (device, r doubles) and spins (device,
- * r*n int8, replica-major); either may be NULL.  SI_ERR_STATE before the
- * first update_best. */
+/* Copy the recorded best energies (device, r doubles; a batch: n_inst*r,
+ * instance i's replicas at offset r*i) and spins (device, r*n int8,
+ * replica-major; a batch: concatenated as at init_batch); either may be
+ * NULL.  SI_ERR_STATE if no best-state update was issued since init or the
+ * last set_state. */
 si_status spring_ising_get_best(si_ctx *ctx, double *best_e, int8_t *best_s);
+
+/* Energy trace of the in-run checks (si_params.energy_every = E > 0): copy
+ * the rows recorded for the checks at steps E, 2E, ... <= t into e (device,
+ * doubles, row k holding the energies of check k: r values, or n_inst*r on
+ * a batch in the order of spring_ising_energy), and the number of rows to
+ * *n_checks (host, may be NULL).  e may be NULL to query the count.  The
+ * values are exact integers for integer J (and field).  SI_ERR_STATE if the
+ * context was created with E = 0. */
+si_status spring_ising_get_energy_trace(si_ctx *ctx, double *e, int32_t *n_checks);
 
 /* Hamiltonian of the spring system, Eq. (7), per replica (device, r
  * doubles): sum_i p_i^2/(2m) + k q_i^2/2 + zeta_t H_Ising(q) with the

@@ -12,7 +12,7 @@ namespace si {
 // Tile ids of the FP32 step kernel (see the tile table in si_step_f32.hip);
 // 0 selects automatically.
 constexpr int32_t TILE_AUTO = 0;
-constexpr int32_t TILE_F32_LAST = 34;
+constexpr int32_t TILE_F32_LAST = 36;
 
 // Work-groups of a launch are dispatched to the eight XCDs in turn (group b
 // runs on XCD b % 8), and each XCD has its own L2.  xcd_tile() renumbers the
@@ -109,7 +109,7 @@ hipError_t launch_step_batch_f32(const StepArgs &a, const BatchDesc *descs, cons
                                  int32_t n_items, int32_t cur, hipStream_t s);
 
 // Step on the BF16 matrix cores (precision forms).
-constexpr int32_t TILE_BF16_LAST = 24;
+constexpr int32_t TILE_BF16_LAST = 34;
 TileShape tile_shape_bf16(int32_t tile);
 struct BStepArgs {
   const void *Ja;         // J plane: bf16 or fp8 [n_pad][n_pad]
@@ -162,6 +162,9 @@ hipError_t launch_energy_i8_batch(const EBatchDesc *descs, const int4 *items, in
 hipError_t launch_energy_f32_batch(const EBatchDesc *descs, const int4 *items, int32_t n_items,
                                    const float *q, float *part, int32_t n_inst, int32_t r,
                                    int32_t r_pad, double *e_real, hipStream_t s);
+hipError_t launch_best_update_batch(const double *e, double *best_e, int32_t *valid,
+                                    const int8_t *S8, int8_t *best_s, const EBatchDesc *descs,
+                                    int32_t n_inst, int32_t r, hipStream_t s);
 hipError_t launch_energy_f32_partial(const float *J, const float *q, const float *h,
                                      float *part, int32_t n_pad, int32_t r_pad,
                                      hipStream_t s);
@@ -173,8 +176,8 @@ hipError_t launch_hamiltonian_partial(const float *J, const float *q, const floa
                                       const float *h, const float *zetas, int32_t t, float k,
                                       float inv_m, float *part, int32_t n_pad, int32_t r_pad,
                                       hipStream_t s);
-hipError_t launch_best_update(const double *e, double *best_e, const int8_t *S8, int8_t *best_s,
-                              int32_t r, int32_t n_pad, hipStream_t s);
+hipError_t launch_best_update(const double *e, double *best_e, int32_t *valid, const int8_t *S8,
+                              int8_t *best_s, int32_t r, int32_t n_pad, hipStream_t s);
 hipError_t launch_fill_f64(double *p, int64_t count, double v, hipStream_t s);
 
 // Exact energy: s = sign(q) as int8 into S8, then G = J8.S8 on int8 MFMA,

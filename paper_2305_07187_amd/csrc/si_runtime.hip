@@ -145,10 +145,20 @@ struct si_ctx {
   int32_t *res_sync = nullptr;  // [0] time-out flag, [64 ..] per-group step counts
   int32_t res_sync_cap = 0;
   hipStream_t cap_stream = nullptr;
-  // in-run best state per replica
+  // best state per replica (per instance and replica on a batch): lowest
+  // energy seen since the last reset and its spins; best_valid[k] == 0 marks
+  // a record that the next update overwrites (reset on the device, so that
+  // captured launch sequences replay correctly)
   double *best_e = nullptr, *e_scratch = nullptr;
   int8_t *best_s = nullptr;
-  bool best_fresh = true;  // next update starts the record
+  int32_t *best_valid = nullptr;
+  bool best_any = false;  // an update was issued since init or the last set_state
+  // in-run energy checks: every e_every steps the energies of all replicas
+  // go to row t / e_every - 1 of the trace [e_rows][out_rows()] and update
+  // the best state
+  int32_t e_every = 0, e_rows = 0;
+  double *etrace = nullptr;
+  int64_t out_rows() const { return n_inst ? (int64_t)n_inst * r : (int64_t)r; }
   // adjoint workspace
   float *adj_ckpt = nullptr, *adj_seg = nullptr, *adj_lam = nullptr;
   uint8_t *adj_mask = nullptr;
@@ -228,6 +238,7 @@ static si_status check_params(const si_params *p) {
   const int32_t last = p->precision == SI_PREC_FP32 ? TILE_F32_LAST : TILE_BF16_LAST;
   if (p->tile < 0 || p->tile > last)
     return fail(SI_ERR_INVALID, "params: unknown tile %d", p->tile);
+  if (p->energy_every < 0) return fail(SI_ERR_INVALID, "params: energy_every must be >= 0");
   return SI_OK;
 }
 
@@ -286,11 +297,14 @@ static int32_t choose_tile_bf16(int32_t n, int32_t r, int num_cus, int32_t preci
   // workgroup of that size, then 128x128 (for the three-plane form the
   // two-slab ring of eight waves), eight-wave 128x64 (single-plane and
   // three-plane forms) and 64x64 direct-to-LDS rings, then register-staged
-  // tiles as the fallback for small problems.
+  // tiles as the fallback for small problems.  Tiles 26 and 28 are the
+  // pipelined twins (bit-identical results) of the three-plane 128x64 tile
+  // and the hi + lo 128x256 tile: 32.1 -> 30.5 us at N=2000, R=1024 and
+  // 482 -> 470 us at N=8000, R=2048.
   static const int32_t pref_bf16j[] = {16, 18, 23, 8, 7, 11, 10, 1, 2, 3};
   static const int32_t pref_fp8j[] = {19, 14, 23, 9, 13, 1, 6, 2, 3};
-  static const int32_t pref_hilo[] = {20, 18, 7, 10, 11, 1, 2, 3};
-  static const int32_t pref_exact[] = {21, 22, 24, 11, 8, 7, 1, 2, 3};
+  static const int32_t pref_hilo[] = {28, 18, 7, 10, 11, 1, 2, 3};
+  static const int32_t pref_exact[] = {21, 22, 26, 11, 8, 7, 1, 2, 3};
 #define SI_PREF(a) order = a, count = (int)(sizeof a / sizeof a[0])
   const int32_t *order;
   int count;
@@ -346,6 +360,29 @@ static int32_t choose_tile(int32_t n, int32_t r, int num_cus) {
     }
   }
   return best;
+}
+
+// Buffers of the best-state record (allocated once, records invalid).
+static hipError_t ensure_best_buffers(si_ctx *c) {
+  if (c->best_e) return hipSuccess;
+  const int64_t rows = c->n_inst ? (int64_t)c->n_inst * c->r : c->r_pad;
+  const int64_t sbytes = c->n_inst ? c->b_stot : (int64_t)c->r_pad * c->n_pad;
+  hipError_t e = c->alloc(&c->best_e, rows);
+  if (e == hipSuccess) e = c->alloc(&c->e_scratch, rows);
+  if (e == hipSuccess) e = c->alloc(&c->best_valid, rows);
+  if (e == hipSuccess) e = c->alloc(&c->best_s, sbytes);
+  if (e == hipSuccess) e = launch_zero_i32(c->best_valid, rows, c->stream);
+  return e;
+}
+
+// In-run energy checks requested at init: the trace and the best record.
+static hipError_t init_energy_checks(si_ctx *c) {
+  c->e_every = c->prm.energy_every;
+  if (c->e_every <= 0) return hipSuccess;
+  c->e_rows = c->prm.total_steps / c->e_every;
+  hipError_t e = c->alloc(&c->etrace, (c->e_rows > 0 ? c->e_rows : 1) * c->out_rows());
+  if (e == hipSuccess) e = ensure_best_buffers(c);
+  return e;
 }
 
 // Hash of the sources and build flags this library was compiled from, set
@@ -419,7 +456,6 @@ si_status spring_ising_init(si_ctx **out, int32_t n, int32_t r, const float *J, 
   } while (0)
   INIT_HIP(hipGetDevice(&c->device));
   INIT_HIP(hipDeviceGetAttribute(&c->num_cus, hipDeviceAttributeMultiprocessorCount, c->device));
-
   // validation of J: one host round trip
   INIT_HIP(c->alloc(&c->flags, 8));
   INIT_HIP(launch_zero_i32(c->flags, 8, c->stream));
@@ -493,6 +529,7 @@ si_status spring_ising_init(si_ctx **out, int32_t n, int32_t r, const float *J, 
                           hipMemcpyHostToDevice, c->stream));
   INIT_HIP(hipMemcpyAsync(c->zeta, c->host_zeta.data(), sizeof(float) * prm->total_steps,
                           hipMemcpyHostToDevice, c->stream));
+  INIT_HIP(init_energy_checks(c));
 #undef INIT_HIP
   c->cur = 0;
   c->t = 0;
@@ -714,6 +751,7 @@ si_status spring_ising_init_batch(si_ctx **out, int32_t n_inst, const int32_t *n
                            hipMemcpyHostToDevice, c->stream));
   BINIT_HIP(hipMemcpyAsync(c->zeta, c->host_zeta.data(), sizeof(float) * prm->total_steps,
                            hipMemcpyHostToDevice, c->stream));
+  BINIT_HIP(init_energy_checks(c));
   BINIT_HIP(hipStreamSynchronize(c->stream));  // host tables may go out of scope
 #undef BINIT_HIP
   c->cur = 0;
@@ -770,6 +808,16 @@ si_status spring_ising_set_field(si_ctx *c, const float *h) {
   return SI_OK;
 }
 
+// In-run energy check after the step that brought the context to time t.
+static si_status record_check(si_ctx *c);
+#define SI_ENERGY_CHECK(c)                                   \
+  do {                                                       \
+    if ((c)->e_every > 0 && (c)->t % (c)->e_every == 0) {    \
+      si_status _st = record_check(c);                       \
+      if (_st != SI_OK) return _st;                          \
+    }                                                        \
+  } while (0)
+
 static si_status do_steps_lowp(si_ctx *c, int32_t n_steps) {
   BStepArgs a;
   a.Ja = c->Ja;
@@ -798,6 +846,7 @@ static si_status do_steps_lowp(si_ctx *c, int32_t n_steps) {
     SI_HIP(c, launch_step_bf16(c->tile, c->prm.precision, a, c->stream));
     c->cur ^= 1;
     c->t += 1;
+    SI_ENERGY_CHECK(c);
   }
   return SI_OK;
 }
@@ -845,6 +894,7 @@ static si_status do_steps_batch(si_ctx *c, int32_t n_steps) {
                                        (int32_t)c->b_items_host.size(), c->cur, c->stream));
       c->cur ^= 1;
       c->t += 1;
+      SI_ENERGY_CHECK(c);
     }
     return SI_OK;
   }
@@ -855,6 +905,7 @@ static si_status do_steps_batch(si_ctx *c, int32_t n_steps) {
                                     c->cur, c->stream));
     c->cur ^= 1;
     c->t += 1;
+    SI_ENERGY_CHECK(c);
   }
   return SI_OK;
 }
@@ -891,6 +942,7 @@ static si_status do_steps(si_ctx *c, int32_t n_steps) {
     SI_HIP(c, launch_step_f32(c->tile, a, c->stream));
     c->cur ^= 1;
     c->t += 1;
+    SI_ENERGY_CHECK(c);
   }
   return SI_OK;
 }
@@ -1029,6 +1081,8 @@ static si_status run_graph(si_ctx *c, int32_t n_steps) {
     hit = &c->graphs.back();
   }
   SI_HIP(c, hipGraphLaunch(hit->exec, c->stream));
+  // the replayed sequence holds the in-run checks of the steps it covers
+  if (c->e_every > 0 && (c->t + n_steps) / c->e_every > c->t / c->e_every) c->best_any = true;
   c->t += n_steps;
   c->cur ^= (n_steps & 1);
   return SI_OK;
@@ -1089,7 +1143,8 @@ si_status spring_ising_run(si_ctx *c, int32_t n_steps) {
   if ((int64_t)c->t + n_steps > c->prm.total_steps)
     return fail(SI_ERR_RANGE, "run: t=%d + n_steps=%d exceeds total_steps=%d", c->t, n_steps,
                 c->prm.total_steps);
-  if (c->resident_min_steps > 0 && n_steps >= c->resident_min_steps && n_steps > 1) {
+  if (c->resident_min_steps > 0 && n_steps >= c->resident_min_steps && n_steps > 1 &&
+      c->e_every == 0) {
     const int32_t groups = resident_groups(c);
     if (groups > 0) return run_resident(c, n_steps, groups);
   }
@@ -1169,6 +1224,13 @@ si_status spring_ising_autotune(si_ctx *c, int32_t steps, int32_t *best_tile, fl
   }
   hipEvent_t e0 = c->tune_ev[0], e1 = c->tune_ev[1];
   const bool lowp = c->qplanes != 0;
+  // candidates' steps record no energy checks (their states are discarded)
+  struct KeepEvery {
+    si_ctx *c;
+    int32_t v;
+    ~KeepEvery() { c->e_every = v; }
+  } keep{c, c->e_every};
+  c->e_every = 0;
   const int32_t last = lowp ? TILE_BF16_LAST : TILE_F32_LAST;
   const int32_t timed = steps - 1 > 0 ? steps - 1 : 1;
   int32_t best = tile0;
@@ -1277,10 +1339,8 @@ si_status spring_ising_spins(si_ctx *c, int8_t *s) {
   return SI_OK;
 }
 
-si_status spring_ising_energy(si_ctx *c, int32_t *e_int, double *e_real) {
-  SI_USABLE(c);
-  if ((e_int && !is_device_ptr(e_int)) || (e_real && !is_device_ptr(e_real)))
-    return fail(SI_ERR_INVALID, "energy: outputs must be device pointers");
+// Energies of the current spins into device outputs (no argument checks).
+static si_status energy_into(si_ctx *c, int32_t *e_int, double *e_real) {
   if (!e_int && !e_real) return SI_OK;
   if (c->n_inst) return batch_energy(c, e_int, e_real);
   // exact int32 path: integer J (and field) with a sum that cannot overflow
@@ -1306,44 +1366,81 @@ si_status spring_ising_energy(si_ctx *c, int32_t *e_int, double *e_real) {
   return SI_OK;
 }
 
-static si_status ensure_best(si_ctx *c) {
-  if (!c->best_e) {
-    SI_HIP(c, c->alloc(&c->best_e, c->r_pad));
-    SI_HIP(c, c->alloc(&c->e_scratch, c->r_pad));
-    SI_HIP(c, c->alloc(&c->best_s, (int64_t)c->r_pad * c->n_pad));
+si_status spring_ising_energy(si_ctx *c, int32_t *e_int, double *e_real) {
+  SI_USABLE(c);
+  if ((e_int && !is_device_ptr(e_int)) || (e_real && !is_device_ptr(e_real)))
+    return fail(SI_ERR_INVALID, "energy: outputs must be device pointers");
+  return energy_into(c, e_int, e_real);
+}
+
+// Best-state update from the energies e of the current spins (out_rows()
+// doubles on the device).
+static si_status best_update_from(si_ctx *c, const double *e) {
+  SI_HIP(c, ensure_best_buffers(c));
+  if (c->n_inst) {
+    SI_HIP(c, launch_sign(c->b_q[c->cur][0], c->S8, (int32_t)(c->b_stot / c->r_pad), c->r_pad,
+                          c->stream));
+    SI_HIP(c, launch_best_update_batch(e, c->best_e, c->best_valid, c->S8, c->best_s, c->eb_desc,
+                                       c->n_inst, c->r, c->stream));
+  } else {
+    SI_HIP(c, launch_sign(c->q[c->cur], c->S8, c->n_pad, c->r_pad, c->stream));
+    SI_HIP(c, launch_best_update(e, c->best_e, c->best_valid, c->S8, c->best_s, c->r, c->n_pad,
+                                 c->stream));
   }
+  c->best_any = true;
   return SI_OK;
+}
+
+static si_status record_check(si_ctx *c) {
+  const int32_t row = c->t / c->e_every - 1;
+  if (row < 0 || row >= c->e_rows) return SI_OK;
+  double *e = c->etrace + (int64_t)row * c->out_rows();
+  si_status st = energy_into(c, nullptr, e);
+  if (st != SI_OK) return st;
+  return best_update_from(c, e);
 }
 
 si_status spring_ising_update_best(si_ctx *c) {
   SI_USABLE(c);
-  if (c->n_inst) return fail(SI_ERR_UNSUPPORTED, "update_best: not available for a batch");
-  si_status st = ensure_best(c);
+  SI_HIP(c, ensure_best_buffers(c));
+  si_status st = energy_into(c, nullptr, c->e_scratch);
   if (st != SI_OK) return st;
-  if (c->best_fresh) {
-    SI_HIP(c, launch_fill_f64(c->best_e, c->r_pad, __builtin_inf(), c->stream));
-    c->best_fresh = false;
-  }
-  st = spring_ising_energy(c, nullptr, c->e_scratch);
-  if (st != SI_OK) return st;
-  SI_HIP(c, launch_sign(c->q[c->cur], c->S8, c->n_pad, c->r_pad, c->stream));
-  SI_HIP(c, launch_best_update(c->e_scratch, c->best_e, c->S8, c->best_s, c->r, c->n_pad,
-                               c->stream));
-  return SI_OK;
+  return best_update_from(c, c->e_scratch);
 }
 
 si_status spring_ising_get_best(si_ctx *c, double *best_e, int8_t *best_s) {
   SI_USABLE(c);
-  if (c->n_inst) return fail(SI_ERR_UNSUPPORTED, "get_best: not available for a batch");
-  if (!c->best_e || c->best_fresh)
-    return fail(SI_ERR_STATE, "get_best: no update_best since init or set_state");
+  if (!c->best_e || !c->best_any)
+    return fail(SI_ERR_STATE, "get_best: no best-state update since init or set_state");
   if ((best_e && !is_device_ptr(best_e)) || (best_s && !is_device_ptr(best_s)))
     return fail(SI_ERR_INVALID, "get_best: outputs must be device pointers");
   if (best_e)
-    SI_HIP(c, hipMemcpyAsync(best_e, c->best_e, sizeof(double) * c->r, hipMemcpyDeviceToDevice,
-                             c->stream));
-  if (best_s)
-    SI_HIP(c, launch_unpack_spins(c->best_s, c->n, c->r, best_s, c->n_pad, c->stream));
+    SI_HIP(c, hipMemcpyAsync(best_e, c->best_e, sizeof(double) * c->out_rows(),
+                             hipMemcpyDeviceToDevice, c->stream));
+  if (best_s) {
+    if (c->n_inst) {
+      for (int32_t i = 0; i < c->n_inst; ++i)
+        SI_HIP(c, launch_unpack_spins(c->best_s + c->b_soff[i], c->b_n[i], c->r,
+                                      best_s + c->b_xoff[i], c->b_npad[i], c->stream));
+    } else {
+      SI_HIP(c, launch_unpack_spins(c->best_s, c->n, c->r, best_s, c->n_pad, c->stream));
+    }
+  }
+  return SI_OK;
+}
+
+si_status spring_ising_get_energy_trace(si_ctx *c, double *e, int32_t *n_checks) {
+  SI_USABLE(c);
+  if (c->e_every <= 0)
+    return fail(SI_ERR_STATE, "get_energy_trace: the context was created with energy_every = 0");
+  if (e && !is_device_ptr(e))
+    return fail(SI_ERR_INVALID, "get_energy_trace: e must be a device pointer");
+  int32_t rows = c->t / c->e_every;
+  if (rows > c->e_rows) rows = c->e_rows;
+  if (n_checks) *n_checks = rows;
+  if (e && rows > 0)
+    SI_HIP(c, hipMemcpyAsync(e, c->etrace, sizeof(double) * rows * c->out_rows(),
+                             hipMemcpyDeviceToDevice, c->stream));
   return SI_OK;
 }
 
@@ -1381,6 +1478,9 @@ si_status spring_ising_set_state(si_ctx *c, const float *x, const float *p, int3
     return fail(SI_ERR_INVALID, "set_state: x and p must be device pointers");
   if (t < 0 || t > c->prm.total_steps)
     return fail(SI_ERR_RANGE, "set_state: t=%d outside [0, %d]", t, c->prm.total_steps);
+  if (c->best_valid)
+    SI_HIP(c, launch_zero_i32(c->best_valid, c->n_inst ? c->out_rows() : c->r_pad, c->stream));
+  c->best_any = false;
   if (c->n_inst) {
     si_status st = batch_set_state(c, x, p);
     if (st == SI_OK) c->t = t;
@@ -1388,7 +1488,6 @@ si_status spring_ising_set_state(si_ctx *c, const float *x, const float *p, int3
   }
   SI_HIP(c, launch_pack_state(x, c->n, c->r, c->q[c->cur], c->n_pad, c->r_pad, c->stream));
   SI_HIP(c, launch_pack_state(p, c->n, c->r, c->p[c->cur], c->n_pad, c->r_pad, c->stream));
-  c->best_fresh = true;
   if (c->qplanes)
     SI_HIP(c, launch_split_planes(c->q[c->cur], c->qb[c->cur], (int64_t)c->n_pad * c->r_pad,
                                   c->qplanes, c->stream));

@@ -207,10 +207,23 @@ __device__ __forceinline__ void wait_vm_barrier_b() {
   asm volatile("s_waitcnt vmcnt(%0)\n\ts_barrier" ::"n"(N) : "memory");
 }
 
-template <int BM_, int BN_, int WM_, int WN_, int BK_, int JFMT_, int QP_, int STAGES_>
+// Also waits for this wave's LDS reads (the slot they read may be refilled
+// once every wave has passed the barrier).
+template <int N>
+__device__ __forceinline__ void wait_vm_lgkm_barrier_b() {
+  asm volatile("s_waitcnt vmcnt(%0) lgkmcnt(0)\n\ts_barrier" ::"n"(N) : "memory");
+}
+
+template <int BM_, int BN_, int WM_, int WN_, int BK_, int JFMT_, int QP_, int STAGES_,
+          int PIPE_ = 0>
 struct Bf16DmaCfg {
   static constexpr int BM = BM_, BN = BN_, WM = WM_, WN = WN_, BK = BK_;
   static constexpr int JFMT = JFMT_, QP = QP_, STAGES = STAGES_;
+  // PIPE = 1: the barrier that hands over slab k + 1 comes before the last
+  // 32-deep step of slab k, whose fragments are already in registers, so
+  // that the first fragments of slab k + 1 are read while the last
+  // matrix-core operations of slab k run.
+  static constexpr int PIPE = PIPE_;
   static constexpr int JP = JFMT == 2 ? 2 : 1;
   static constexpr int EA = JFMT == 1 ? 1 : 2;  // bytes per J element in LDS
   static constexpr int MB = 32;
@@ -315,66 +328,130 @@ __device__ __forceinline__ void bf16_mainloop_dma(const BStepArgs &a, int m0, in
 #pragma unroll
   for (int s = 0; s < S - 1; ++s)
     if (s < nk) issue(s, s);
-  // ring slots read and written this iteration, kept as counters
-  int rd = 0, wr = S - 1;
-  for (int kt = 0; kt < nk; ++kt) {
-    if (kt + S - 1 < nk) {
-      wait_vm_barrier_b<(S - 2) * C::L>();
-      issue(kt + S - 1, wr);
-    } else {
-      wait_vm_barrier_b<0>();
-    }
-    wr = wr + 1 == S ? 0 : wr + 1;
-    const uint8_t *st = smem + rd * C::SLOT;
-    rd = rd + 1 == S ? 0 : rd + 1;
+  // Raw fragments of one 32-deep step: FP8 J as one 16-byte chunk per row
+  // block (both halves of the step), BF16 planes as two 16-byte chunks.
+  constexpr int AC = C::JFMT == 1 ? 1 : 2;
+  struct Frag {
+    uintx4 fa[C::JP][C::TM][AC];
+    uintx4 fb[C::QP][C::TN][2];
+  };
+  auto read_frag = [&](const uint8_t *st, int kk, Frag &f) {
 #pragma unroll
-    for (int kk = 0; kk < C::BK; kk += 32) {
-      bf16x8 fa[C::JP][C::TM][2], fb[C::QP][C::TN][2];
+    for (int i = 0; i < C::TM; ++i) {
+      const int r = wy * C::WTM + i * 32 + lrow;
+      if (C::JFMT == 1) {
+        const int ch = (kk + 16 * h) / 16;  // 16 fp8 per chunk
+        f.fa[0][i][0] =
+            *reinterpret_cast<const uintx4 *>(st + r * C::ROWA + ((ch ^ lds_swz<C::CHA>(r)) << 4));
+      } else {
 #pragma unroll
-      for (int i = 0; i < C::TM; ++i) {
-        const int r = wy * C::WTM + i * 32 + lrow;
-        if (C::JFMT == 1) {
-          const int ch = (kk + 16 * h) / 16;  // 16 fp8 per chunk
-          const uintx4 w = *reinterpret_cast<const uintx4 *>(st + r * C::ROWA +
-                                                             ((ch ^ lds_swz<C::CHA>(r)) << 4));
-          fa[0][i][0] = fp8x8_to_bf16x8(w[0], w[1]);
-          fa[0][i][1] = fp8x8_to_bf16x8(w[2], w[3]);
-        } else {
-#pragma unroll
-          for (int pl = 0; pl < C::JP; ++pl)
-#pragma unroll
-            for (int sidx = 0; sidx < 2; ++sidx) {
-              const int ch = (kk + 16 * h + 8 * sidx) / 8;  // 8 bf16 per chunk
-              fa[pl][i][sidx] = *reinterpret_cast<const bf16x8 *>(
-                  st + pl * C::A_BYTES + r * C::ROWA + ((ch ^ lds_swz<C::CHA>(r)) << 4));
-            }
-        }
-      }
-#pragma unroll
-      for (int j = 0; j < C::TN; ++j) {
-        const int r = wx * C::WTN + j * 32 + lrow;
-#pragma unroll
-        for (int pl = 0; pl < C::QP; ++pl)
+        for (int pl = 0; pl < C::JP; ++pl)
 #pragma unroll
           for (int sidx = 0; sidx < 2; ++sidx) {
-            const int ch = (kk + 16 * h + 8 * sidx) / 8;
-            fb[pl][j][sidx] = *reinterpret_cast<const bf16x8 *>(
-                st + C::JP * C::A_BYTES + pl * C::B_BYTES + r * C::ROWB + ((ch ^ lds_swz<C::CHB>(r)) << 4));
+            const int ch = (kk + 16 * h + 8 * sidx) / 8;  // 8 bf16 per chunk
+            f.fa[pl][i][sidx] = *reinterpret_cast<const uintx4 *>(
+                st + pl * C::A_BYTES + r * C::ROWA + ((ch ^ lds_swz<C::CHA>(r)) << 4));
           }
       }
+    }
 #pragma unroll
-      for (int sidx = 0; sidx < 2; ++sidx)
+    for (int j = 0; j < C::TN; ++j) {
+      const int r = wx * C::WTN + j * 32 + lrow;
 #pragma unroll
-        for (int i = 0; i < C::TM; ++i)
+      for (int pl = 0; pl < C::QP; ++pl)
 #pragma unroll
-          for (int j = 0; j < C::TN; ++j)
+        for (int sidx = 0; sidx < 2; ++sidx) {
+          const int ch = (kk + 16 * h + 8 * sidx) / 8;
+          f.fb[pl][j][sidx] = *reinterpret_cast<const uintx4 *>(
+              st + C::JP * C::A_BYTES + pl * C::B_BYTES + r * C::ROWB + ((ch ^ lds_swz<C::CHB>(r)) << 4));
+        }
+    }
+  };
+  auto mma_frag = [&](const Frag &f) {
+    bf16x8 fa[C::JP][C::TM][2];
 #pragma unroll
-            for (int pa = 0; pa < C::JP; ++pa)
+    for (int i = 0; i < C::TM; ++i) {
+      if (C::JFMT == 1) {
+        fa[0][i][0] = fp8x8_to_bf16x8(f.fa[0][i][0][0], f.fa[0][i][0][1]);
+        fa[0][i][1] = fp8x8_to_bf16x8(f.fa[0][i][0][2], f.fa[0][i][0][3]);
+      } else {
 #pragma unroll
-              for (int pb = 0; pb < C::QP; ++pb)
-                acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[pa][i][sidx],
-                                                                    fb[pb][j][sidx], acc[i][j],
-                                                                    0, 0, 0);
+        for (int pl = 0; pl < C::JP; ++pl)
+#pragma unroll
+          for (int sidx = 0; sidx < 2; ++sidx)
+            fa[pl][i][sidx] = __builtin_bit_cast(bf16x8, f.fa[pl][i][AC == 2 ? sidx : 0]);
+      }
+    }
+#pragma unroll
+    for (int sidx = 0; sidx < 2; ++sidx)
+#pragma unroll
+      for (int i = 0; i < C::TM; ++i)
+#pragma unroll
+        for (int j = 0; j < C::TN; ++j)
+#pragma unroll
+          for (int pa = 0; pa < C::JP; ++pa)
+#pragma unroll
+            for (int pb = 0; pb < C::QP; ++pb)
+              acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                  fa[pa][i][sidx], __builtin_bit_cast(bf16x8, f.fb[pb][j][sidx]), acc[i][j], 0, 0,
+                  0);
+  };
+  if constexpr (C::PIPE) {
+    constexpr int NKS = C::BK / 32;
+    Frag fr[2];
+    int rd = 0, wr = S - 1;
+    if (nk > 0) {
+      if (S - 1 < nk) {
+        wait_vm_barrier_b<(S - 2) * C::L>();
+        issue(S - 1, wr);
+      } else {
+        wait_vm_barrier_b<0>();
+      }
+      wr = wr + 1 == S ? 0 : wr + 1;
+      read_frag(smem, 0, fr[0]);
+    }
+    for (int kt = 0; kt < nk; ++kt) {
+      const uint8_t *st = smem + rd * C::SLOT;
+#pragma unroll
+      for (int ks = 0; ks < NKS; ++ks) {
+        const int cur = ks & 1;
+        if (ks + 1 < NKS) {
+          read_frag(st, (ks + 1) * 32, fr[cur ^ 1]);
+        } else if (kt + 1 < nk) {
+          // every wave holds its fragments of slab kt and slab kt + 1 has
+          // landed: slot rd may be refilled with slab kt + S
+          if (kt + S < nk) {
+            wait_vm_lgkm_barrier_b<(S - 2) * C::L>();
+            issue(kt + S, wr);
+          } else {
+            wait_vm_lgkm_barrier_b<0>();
+          }
+          wr = wr + 1 == S ? 0 : wr + 1;
+          rd = rd + 1 == S ? 0 : rd + 1;
+          read_frag(smem + rd * C::SLOT, 0, fr[cur ^ 1]);
+        }
+        mma_frag(fr[cur]);
+      }
+    }
+  } else {
+    // ring slots read and written this iteration, kept as counters
+    int rd = 0, wr = S - 1;
+    for (int kt = 0; kt < nk; ++kt) {
+      if (kt + S - 1 < nk) {
+        wait_vm_barrier_b<(S - 2) * C::L>();
+        issue(kt + S - 1, wr);
+      } else {
+        wait_vm_barrier_b<0>();
+      }
+      wr = wr + 1 == S ? 0 : wr + 1;
+      const uint8_t *st = smem + rd * C::SLOT;
+      rd = rd + 1 == S ? 0 : rd + 1;
+#pragma unroll
+      for (int kk = 0; kk < C::BK; kk += 32) {
+        Frag f;
+        read_frag(st, kk, f);
+        mma_frag(f);
+      }
     }
   }
   wait_vm_barrier_b<0>();
@@ -572,36 +649,49 @@ static hipError_t launch_bd(const BStepArgs &a, hipStream_t s) {
 // the problem has that many blocks (N = 2000, R = 1024), and tile 24 the
 // same for the three-plane form over 64-deep slabs.
 #define SI_BF16_TILES(X)         \
-  X(1, 64, 64, 2, 2, 64, 0)      \
-  X(2, 64, 128, 2, 2, 64, 0)     \
-  X(3, 128, 64, 2, 2, 64, 0)     \
-  X(4, 128, 128, 2, 2, 64, 0)    \
-  X(5, 128, 128, 2, 4, 64, 0)    \
-  X(6, 64, 64, 2, 2, 128, 0)     \
-  X(7, 64, 64, 2, 2, 64, 3)      \
-  X(8, 64, 64, 2, 2, 64, 4)      \
-  X(9, 64, 64, 2, 2, 128, 3)     \
-  X(10, 64, 128, 2, 2, 64, 3)    \
-  X(11, 128, 64, 2, 2, 64, 3)    \
-  X(12, 128, 128, 2, 2, 64, 3)   \
-  X(13, 64, 64, 2, 2, 128, 4)    \
-  X(14, 128, 128, 2, 2, 128, 3)  \
-  X(15, 128, 128, 2, 2, 64, 4)   \
-  X(16, 128, 256, 2, 4, 64, 3)   \
-  X(17, 256, 128, 4, 2, 64, 3)   \
-  X(18, 128, 128, 2, 4, 64, 3)   \
-  X(19, 128, 128, 4, 2, 128, 3)  \
-  X(20, 128, 256, 2, 4, 64, 2)   \
-  X(21, 256, 128, 4, 2, 64, 2)   \
-  X(22, 128, 128, 2, 4, 64, 2)   \
-  X(23, 128, 64, 4, 2, 128, 3)   \
-  X(24, 128, 64, 4, 2, 64, 3)
+  X(1, 64, 64, 2, 2, 64, 0, 0)      \
+  X(2, 64, 128, 2, 2, 64, 0, 0)     \
+  X(3, 128, 64, 2, 2, 64, 0, 0)     \
+  X(4, 128, 128, 2, 2, 64, 0, 0)    \
+  X(5, 128, 128, 2, 4, 64, 0, 0)    \
+  X(6, 64, 64, 2, 2, 128, 0, 0)     \
+  X(7, 64, 64, 2, 2, 64, 3, 0)      \
+  X(8, 64, 64, 2, 2, 64, 4, 0)      \
+  X(9, 64, 64, 2, 2, 128, 3, 0)     \
+  X(10, 64, 128, 2, 2, 64, 3, 0)    \
+  X(11, 128, 64, 2, 2, 64, 3, 0)    \
+  X(12, 128, 128, 2, 2, 64, 3, 0)   \
+  X(13, 64, 64, 2, 2, 128, 4, 0)    \
+  X(14, 128, 128, 2, 2, 128, 3, 0)  \
+  X(15, 128, 128, 2, 2, 64, 4, 0)   \
+  X(16, 128, 256, 2, 4, 64, 3, 0)   \
+  X(17, 256, 128, 4, 2, 64, 3, 0)   \
+  X(18, 128, 128, 2, 4, 64, 3, 0)   \
+  X(19, 128, 128, 4, 2, 128, 3, 0)  \
+  X(20, 128, 256, 2, 4, 64, 2, 0)   \
+  X(21, 256, 128, 4, 2, 64, 2, 0)   \
+  X(22, 128, 128, 2, 4, 64, 2, 0)   \
+  X(23, 128, 64, 4, 2, 128, 3, 0)   \
+  X(24, 128, 64, 4, 2, 64, 3, 0)   \
+  X(25, 128, 64, 4, 2, 128, 3, 1)  \
+  X(26, 128, 64, 4, 2, 64, 3, 1)   \
+  X(27, 128, 128, 4, 2, 128, 3, 1) \
+  X(28, 128, 256, 2, 4, 64, 2, 1)  \
+  X(29, 64, 64, 2, 2, 64, 3, 1)    \
+  X(30, 128, 64, 4, 2, 128, 4, 1)  \
+  X(31, 128, 64, 4, 2, 64, 4, 1)   \
+  X(32, 128, 256, 2, 4, 64, 3, 1)  \
+  X(33, 256, 128, 4, 2, 64, 2, 1)  \
+  X(34, 128, 128, 2, 4, 64, 2, 1)
 
 TileShape tile_shape_bf16(int32_t tile) {
   switch (tile) {
-#define SI_SHAPE(id, bm, bn, wm, wn, bk, st) \
+#define SI_SHAPE(id, bm, bn, wm, wn, bk, st, pp) \
   case id:                                   \
-    return {bm, bn, "step_bf16_" #bm "x" #bn "_w" #wm "x" #wn "_k" #bk "_s" #st, bk};
+    return {bm, bn,                          \
+            pp ? "step_bf16_" #bm "x" #bn "_w" #wm "x" #wn "_k" #bk "_s" #st "_p1" \
+               : "step_bf16_" #bm "x" #bn "_w" #wm "x" #wn "_k" #bk "_s" #st,       \
+            bk};
     SI_BF16_TILES(SI_SHAPE)
 #undef SI_SHAPE
     default: return {0, 0, "invalid", 0};
@@ -622,14 +712,14 @@ static hipError_t launch_b(const BStepArgs &a, hipStream_t s) {
   return hipGetLastError();
 }
 
-template <int BM, int BN, int WM, int WN, int BK, int ST, int JFMT, int QP>
+template <int BM, int BN, int WM, int WN, int BK, int ST, int JFMT, int QP, int PP>
 static hipError_t launch_sel(const BStepArgs &a, hipStream_t s) {
   if constexpr (ST == 0) {
     return launch_b<Bf16Cfg<BM, BN, WM, WN, BK, JFMT, QP>>(a, s);
   } else if constexpr (JFMT == 1 && BK < 128) {
     return hipErrorInvalidValue;  // FP8 rows must be 128 bytes for the swizzle
   } else {
-    using C = Bf16DmaCfg<BM, BN, WM, WN, BK, JFMT, QP, ST>;
+    using C = Bf16DmaCfg<BM, BN, WM, WN, BK, JFMT, QP, ST, PP>;
     if constexpr (C::LDS_BYTES > 160 * 1024)
       return hipErrorInvalidValue;
     else
@@ -637,22 +727,22 @@ static hipError_t launch_sel(const BStepArgs &a, hipStream_t s) {
   }
 }
 
-template <int BM, int BN, int WM, int WN, int BK, int ST, int JFMT, int QP>
+template <int BM, int BN, int WM, int WN, int BK, int ST, int JFMT, int QP, int PP>
 static constexpr bool sel_valid() {
   if constexpr (ST == 0)
     return true;
   else if constexpr (JFMT == 1 && BK < 128)
     return false;
   else
-    return Bf16DmaCfg<BM, BN, WM, WN, BK, JFMT, QP, ST>::LDS_BYTES <= 160 * 1024;
+    return Bf16DmaCfg<BM, BN, WM, WN, BK, JFMT, QP, ST, PP>::LDS_BYTES <= 160 * 1024;
 }
 
 template <int JFMT, int QP>
 static bool valid_fmt(int32_t tile) {
   switch (tile) {
-#define SI_VALID(id, bm, bn, wm, wn, bk, st) \
+#define SI_VALID(id, bm, bn, wm, wn, bk, st, pp) \
   case id:                                   \
-    return sel_valid<bm, bn, wm, wn, bk, st, JFMT, QP>();
+    return sel_valid<bm, bn, wm, wn, bk, st, JFMT, QP, pp>();
     SI_BF16_TILES(SI_VALID)
 #undef SI_VALID
     default: return false;
@@ -672,9 +762,9 @@ bool tile_valid_bf16(int32_t tile, int32_t precision) {
 template <int JFMT, int QP>
 static hipError_t launch_fmt(int32_t tile, const BStepArgs &a, hipStream_t s) {
   switch (tile) {
-#define SI_LAUNCH(id, bm, bn, wm, wn, bk, st) \
+#define SI_LAUNCH(id, bm, bn, wm, wn, bk, st, pp) \
   case id:                                    \
-    return launch_sel<bm, bn, wm, wn, bk, st, JFMT, QP>(a, s);
+    return launch_sel<bm, bn, wm, wn, bk, st, JFMT, QP, pp>(a, s);
     SI_BF16_TILES(SI_LAUNCH)
 #undef SI_LAUNCH
     default: return hipErrorInvalidValue;

@@ -232,10 +232,12 @@ __global__ __launch_bounds__(C::NT) void step_batch_f32_kernel(StepArgs a,
 
 TileShape tile_shape(int32_t tile) {
   switch (tile) {
-#define SI_SHAPE(id, bm, bn, wm, wn, mb, bk, st, ks) \
+#define SI_SHAPE(id, bm, bn, wm, wn, mb, bk, st, ks, pp) \
   case id:                                           \
     return {bm, bn,                                  \
-            "step_f32_" #bm "x" #bn "_w" #wm "x" #wn "_mfma" #mb "_k" #bk "_s" #st "_a" #ks, bk};
+            pp ? "step_f32_" #bm "x" #bn "_w" #wm "x" #wn "_mfma" #mb "_k" #bk "_s" #st "_a" #ks "_p1" \
+               : "step_f32_" #bm "x" #bn "_w" #wm "x" #wn "_mfma" #mb "_k" #bk "_s" #st "_a" #ks,    \
+            bk};
     SI_F32_TILES(SI_SHAPE)
 #undef SI_SHAPE
     default: return {0, 0, "invalid", 0};
@@ -292,10 +294,10 @@ static hipError_t resident_launch(const StepArgs &a, const ResidentArgs &r, hipS
 hipError_t resident_f32_groups_per_cu(int32_t tile, int32_t order, int32_t wall, int *groups) {
   *groups = 0;
   switch (tile) {
-#define SI_RES_Q(id, bm, bn, wm, wn, mb, bk, st, ks)                                  \
+#define SI_RES_Q(id, bm, bn, wm, wn, mb, bk, st, ks, pp)                                  \
   case id:                                                                           \
     if constexpr (SI_HAS_RESIDENT(id))                                               \
-      return resident_groups<F32Cfg<bm, bn, wm, wn, mb, bk, st, ks>>(order, wall, groups); \
+      return resident_groups<F32Cfg<bm, bn, wm, wn, mb, bk, st, ks, pp>>(order, wall, groups); \
     else                                                                             \
       return hipSuccess;
     SI_F32_TILES(SI_RES_Q)
@@ -307,10 +309,10 @@ hipError_t resident_f32_groups_per_cu(int32_t tile, int32_t order, int32_t wall,
 hipError_t launch_resident_f32(int32_t tile, const StepArgs &a, const ResidentArgs &r,
                                hipStream_t s) {
   switch (tile) {
-#define SI_RES_L(id, bm, bn, wm, wn, mb, bk, st, ks)                    \
+#define SI_RES_L(id, bm, bn, wm, wn, mb, bk, st, ks, pp)                    \
   case id:                                                             \
     if constexpr (SI_HAS_RESIDENT(id))                                 \
-      return resident_launch<F32Cfg<bm, bn, wm, wn, mb, bk, st, ks>>(a, r, s); \
+      return resident_launch<F32Cfg<bm, bn, wm, wn, mb, bk, st, ks, pp>>(a, r, s); \
     else                                                               \
       return hipErrorInvalidValue;
     SI_F32_TILES(SI_RES_L)
@@ -341,9 +343,9 @@ hipError_t launch_step_batch_f32(const StepArgs &a, const BatchDesc *descs, cons
 hipError_t launch_step_f32(int32_t tile, const StepArgs &a, hipStream_t s) {
   if (a.ksplit > 1) return launch_step_f32_split(tile, a, s);
   switch (tile) {
-#define SI_LAUNCH(id, bm, bn, wm, wn, mb, bk, st, ks) \
+#define SI_LAUNCH(id, bm, bn, wm, wn, mb, bk, st, ks, pp) \
   case id:                                            \
-    return launch_cfg<F32Cfg<bm, bn, wm, wn, mb, bk, st, ks>>(a, s);
+    return launch_cfg<F32Cfg<bm, bn, wm, wn, mb, bk, st, ks, pp>>(a, s);
     SI_F32_TILES(SI_LAUNCH)
 #undef SI_LAUNCH
     default: return hipErrorInvalidValue;
@@ -513,23 +515,53 @@ hipError_t launch_hamiltonian_partial(const float *J, const float *q, const floa
   return hipGetLastError();
 }
 
-// Keep, per replica, the lowest energy seen and the spins that had it.
-__global__ void best_update_kernel(const double *e, double *best_e, const int8_t *S8,
-                                   int8_t *best_s, int n_pad) {
-  const int r = blockIdx.x;
-  const double en = e[r];
-  if (!(en < best_e[r])) return;  // block-uniform decision
-  const int8_t *src = S8 + (size_t)r * n_pad;
-  int8_t *dst = best_s + (size_t)r * n_pad;
+// Keep, per replica, the lowest energy seen and the spins that had it.  A
+// replica whose record is not valid (valid[r] == 0: nothing recorded since
+// the last reset) takes the current energy unconditionally.  The reset is a
+// device flag so that captured launch sequences replay correctly.
+__device__ __forceinline__ void best_update_one(double en, double *best_e, int32_t *valid,
+                                                const int8_t *src, int8_t *dst, int n_pad) {
+  if (*valid && !(en < *best_e)) return;  // block-uniform decision
   for (int i = threadIdx.x * 4; i < n_pad; i += blockDim.x * 4)
     *reinterpret_cast<char4 *>(dst + i) = *reinterpret_cast<const char4 *>(src + i);
   __syncthreads();
-  if (threadIdx.x == 0) best_e[r] = en;
+  if (threadIdx.x == 0) {
+    *best_e = en;
+    *valid = 1;
+  }
 }
 
-hipError_t launch_best_update(const double *e, double *best_e, const int8_t *S8, int8_t *best_s,
-                              int32_t r, int32_t n_pad, hipStream_t s) {
-  best_update_kernel<<<r, 256, 0, s>>>(e, best_e, S8, best_s, n_pad);
+__global__ void best_update_kernel(const double *e, double *best_e, int32_t *valid,
+                                   const int8_t *S8, int8_t *best_s, int n_pad) {
+  const int r = blockIdx.x;
+  best_update_one(e[r], best_e + r, valid + r, S8 + (size_t)r * n_pad,
+                  best_s + (size_t)r * n_pad, n_pad);
+}
+
+// Batch: block i * r + col updates replica col of instance i (energies and
+// records in the instances-by-replicas order of the batch outputs; spins in
+// the batch's state layout).
+__global__ void best_update_batch_kernel(const double *e, double *best_e, int32_t *valid,
+                                         const int8_t *S8, int8_t *best_s,
+                                         const EBatchDesc *__restrict__ descs, int r) {
+  const int64_t idx = blockIdx.x;
+  const int i = (int)(idx / r), col = (int)(idx % r);
+  const EBatchDesc d = descs[i];
+  const size_t off = (size_t)d.soff + (size_t)col * d.n_pad;
+  best_update_one(e[idx], best_e + idx, valid + idx, S8 + off, best_s + off, d.n_pad);
+}
+
+hipError_t launch_best_update(const double *e, double *best_e, int32_t *valid, const int8_t *S8,
+                              int8_t *best_s, int32_t r, int32_t n_pad, hipStream_t s) {
+  best_update_kernel<<<r, 256, 0, s>>>(e, best_e, valid, S8, best_s, n_pad);
+  return hipGetLastError();
+}
+
+hipError_t launch_best_update_batch(const double *e, double *best_e, int32_t *valid,
+                                    const int8_t *S8, int8_t *best_s, const EBatchDesc *descs,
+                                    int32_t n_inst, int32_t r, hipStream_t s) {
+  best_update_batch_kernel<<<(unsigned)((int64_t)n_inst * r), 256, 0, s>>>(e, best_e, valid, S8,
+                                                                         best_s, descs, r);
   return hipGetLastError();
 }
 

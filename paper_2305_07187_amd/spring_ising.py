@@ -43,6 +43,7 @@ class si_params(ctypes.Structure):
         ("qmax", ctypes.c_float), ("pmax", ctypes.c_float),
         ("order", ctypes.c_int32), ("wall", ctypes.c_int32),
         ("precision", ctypes.c_int32), ("tile", ctypes.c_int32),
+        ("energy_every", ctypes.c_int32),
     ]
 
 
@@ -99,6 +100,7 @@ _SIGNATURES = {
     "spring_ising_init_batch": [ctypes.POINTER(_P), _I, _P, _I, _P, _P, _P,
                                 ctypes.POINTER(si_params), _P],
     "spring_ising_debug_inject_hip_error": [_P, _I],
+    "spring_ising_get_energy_trace": [_P, _P, ctypes.POINTER(_I)],
     "spring_ising_destroy": [_P],
 }
 
@@ -141,6 +143,16 @@ def last_error() -> str:
 
 def spring_ising_build_id() -> str:
     return load_library().spring_ising_build_id().decode()
+
+
+def spring_ising_get_energy_trace(ctx, e=None):
+    """Copy the recorded in-run energy checks into e (float64 CUDA tensor, or
+    None to query); returns the number of rows recorded."""
+    import torch
+    k = ctypes.c_int32()
+    _check(load_library().spring_ising_get_energy_trace(ctx, _ptr(e, torch.float64, name="e"),
+                                                       ctypes.byref(k)))
+    return k.value
 
 
 def spring_ising_debug_inject_hip_error(ctx, n):
@@ -413,6 +425,27 @@ class SpringIsingBatch:
     def info(self):
         return spring_ising_info(self.ctx)
 
+    def update_best(self):
+        spring_ising_update_best(self.ctx)
+
+    def best(self):
+        """(best energies as a list per instance, best spins per instance)."""
+        import torch
+        k = len(self.ns)
+        e = torch.empty(k * self.r, dtype=torch.float64, device=self.device)
+        s = torch.empty(self.offsets[-1], dtype=torch.int8, device=self.device)
+        spring_ising_get_best(self.ctx, e, s)
+        return [e[i * self.r:(i + 1) * self.r] for i in range(k)], self._split(s)
+
+    def energy_trace(self):
+        """In-run checks so far: float64 tensor [checks, n_inst, R]."""
+        import torch
+        rows = spring_ising_get_energy_trace(self.ctx, None)
+        e = torch.empty(max(rows, 1) * len(self.ns) * self.r, dtype=torch.float64,
+                        device=self.device)
+        spring_ising_get_energy_trace(self.ctx, e)
+        return e[:rows * len(self.ns) * self.r].view(rows, len(self.ns), self.r)
+
 
 class SpringIsing:
     """Owns one context; torch tensors carry inputs and outputs.
@@ -504,6 +537,14 @@ class SpringIsing:
 
     def update_best(self):
         spring_ising_update_best(self.ctx)
+
+    def energy_trace(self):
+        """In-run checks so far: float64 tensor [checks, R]."""
+        import torch
+        rows = spring_ising_get_energy_trace(self.ctx, None)
+        e = torch.empty(max(rows, 1) * self.r, dtype=torch.float64, device=self.device)
+        spring_ising_get_energy_trace(self.ctx, e)
+        return e[:rows * self.r].view(rows, self.r)
 
     def best(self):
         import torch

@@ -49,16 +49,16 @@ def test_header_compiles_standalone(tmp_path, std, compiler):
         pytest.skip(f"{compiler} missing")
     src = tmp_path / ("t.c" if compiler == "gcc" else "t.cpp")
     src.write_text('#include "spring_ising.h"\nint main(void){ si_params p; si_info i; '
-                   '(void)p; (void)i; return (int)sizeof(si_params) - 52; }\n')
+                   '(void)p; (void)i; return (int)sizeof(si_params) - 56; }\n')
     r = subprocess.run([compiler, std, "-Wall", "-Werror", "-pedantic", "-I",
                         os.path.join(ROOT, "include"), str(src), "-o", str(tmp_path / "t")],
                        capture_output=True, text=True)
     assert r.returncode == 0, r.stderr
-    assert subprocess.run([str(tmp_path / "t")]).returncode == 0  # struct size fixed at 52
+    assert subprocess.run([str(tmp_path / "t")]).returncode == 0  # struct size fixed at 56
 
 
 def test_struct_layouts_match_binding():
-    assert ctypes.sizeof(si.si_params) == 52
+    assert ctypes.sizeof(si.si_params) == 56
     assert ctypes.sizeof(si.si_info) == 4 * 12 + 8 + 64 + 4 * 2
 
 

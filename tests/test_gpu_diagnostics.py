@@ -57,3 +57,118 @@ def test_best_state_tracking():
     assert np.all(be <= e_final)
     announce(f"  best-along-run mean {be.mean():.1f} vs final mean {e_final.mean():.1f}")
     m.close()
+
+
+def _chunked_energies(si, make, S, every, exact):
+    """Reference for the in-run checks: the same run in chunks of `every`
+    steps with an explicit energy call after each chunk (no in-run checks)."""
+    import torch
+    m = make(0)
+    rows = []
+    for _ in range(S // every):
+        m.run(every)
+        rows.append(m.energy(exact=exact).double())
+    torch.cuda.synchronize()
+    m.close()
+    return torch.stack(rows)
+
+
+@pytest.mark.parametrize("precision,kind", [("fp32", "pm1"), ("bf16x_fp8j", "pm1"),
+                                            ("fp32", "gauss"), ("bf16x_hiloj", "gauss")])
+def test_in_run_energy_checks_match_explicit_energies(precision, kind):
+    # With energy_every = E the library records, after every E-th step and on
+    # the stream, the energies of all replicas and updates the best state.
+    # The trace equals explicit energy calls at the same steps, bit for bit
+    # (same kernels), and the best record equals the running minimum.
+    import torch
+    si = ensure_built()
+    announce(f"in-run energy checks ({precision}, {kind} couplings)")
+    n, r, S, every = 300, 64, 400, 25
+    Jn = instances.make_J(n, kind, 11)
+    J, x0 = to_dev(Jn), to_dev(instances.make_x0(n, r, 11))
+    make = lambda e: si.SpringIsing(J, x0, total_steps=S, precision=precision, energy_every=e)
+    exact = kind == "pm1"
+    ref = _chunked_energies(si, make, S, every, exact)
+    m = make(every)
+    assert m.energy_trace().shape == (0, r)
+    m.run(130)
+    m.run(S - 130)                     # checks do not depend on run() boundaries
+    tr = m.energy_trace()
+    be, bs = m.best()
+    torch.cuda.synchronize()
+    assert tr.shape == (S // every, r)
+    assert torch.equal(tr, ref)
+    assert torch.equal(be, tr.min(dim=0).values)
+    if exact:   # the recorded spins carry the recorded energies (Eq. (1) on the host)
+        np.testing.assert_array_equal(
+            oracle.ising_energy(Jn, bs.cpu().numpy().T.astype(np.int64)), be.cpu().numpy())
+    # a rewind resets the record and the row count
+    m.set_state(x0, None, 0)
+    with pytest.raises(si.SpringIsingError) as e:
+        m.best()
+    assert e.value.status == si.SI_ERR_STATE
+    m.run(60)
+    tr2 = m.energy_trace()
+    be2, _ = m.best()
+    torch.cuda.synchronize()
+    assert tr2.shape == (2, r) and torch.equal(tr2, ref[:2])
+    assert torch.equal(be2, ref[:2].min(dim=0).values)
+    m.close()
+
+
+def test_in_run_checks_inside_captured_graphs():
+    # The checks are launched with the steps, so captured launch sequences
+    # contain them; the best record's reset is a device flag, so a replay
+    # after a rewind starts a fresh record exactly as direct launches do.
+    import torch
+    si = ensure_built()
+    announce("in-run checks inside captured graphs")
+    n, r, S, every = 256, 64, 200, 20
+    J, x0 = to_dev(instances.make_pm1(n, 12)), to_dev(instances.make_x0(n, r, 12))
+    d = si.SpringIsing(J, x0, total_steps=S, energy_every=every)
+    d.run(S)
+    trd, (bed, bsd) = d.energy_trace(), d.best()
+    g = si.SpringIsing(J, x0, total_steps=S, energy_every=every)
+    g.set_graph(50)
+    for rep in range(3):
+        g.set_state(x0, None, 0)
+        g.run(100)
+        g.run(100)
+        g.energy()                   # eager work between replays
+        tr, (be, bs) = g.energy_trace(), g.best()
+        torch.cuda.synchronize()
+        assert torch.equal(tr, trd) and torch.equal(be, bed) and torch.equal(bs, bsd), rep
+    d.close()
+    g.close()
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x_mixedj"])
+def test_in_run_checks_on_a_batch(precision):
+    import torch
+    si = ensure_built()
+    announce(f"in-run checks on a batch ({precision})")
+    specs = [(100, "pm1"), (260, "gauss"), (64, "pm1"), (130, "gauss")]
+    r, S, every = 64, 120, 30
+    Jn = [instances.make_J(n, k, 30 + i) for i, (n, k) in enumerate(specs)]
+    Js = [to_dev(a) for a in Jn]
+    xs = [to_dev(instances.make_x0(n, r, 30 + i)) for i, (n, k) in enumerate(specs)]
+    ref = si.SpringIsingBatch(Js, xs, total_steps=S, precision=precision)
+    rows = []
+    for _ in range(S // every):
+        ref.run(every)
+        rows.append(torch.stack(ref.energy(exact=False)))
+    ref.close()
+    b = si.SpringIsingBatch(Js, xs, total_steps=S, precision=precision, energy_every=every)
+    b.set_graph(S)
+    b.run(S)
+    tr = b.energy_trace()
+    be, bs = b.best()
+    torch.cuda.synchronize()
+    assert torch.equal(tr, torch.stack(rows))
+    for i, (n, kind) in enumerate(specs):
+        assert torch.equal(be[i], tr[:, i, :].min(dim=0).values), i
+        if kind == "pm1":
+            np.testing.assert_array_equal(
+                oracle.ising_energy(Jn[i], bs[i].cpu().numpy().T.astype(np.int64)),
+                be[i].cpu().numpy())
+    b.close()
