@@ -268,6 +268,26 @@ si_status spring_ising_spins(si_ctx *ctx, int8_t *s);
  * instances, then real ones), with the values of its single-instance call. */
 si_status spring_ising_energy(si_ctx *ctx, int32_t *e_int, double *e_real);
 
+/* Allocation-free variant of spring_ising_energy, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving
+ * loops): the exact int32 energy of Eq. (1), per replica, of s = sign(x)
+ * (+1 for x >= 0, also -0.0) for caller-owned couplings and positions, with
+ * no context.
+ *   n, r : 1 <= n <= 65536 and 1 <= r <= 65536; SI_ERR_INVALID beyond.
+ *   J    : device, n*n floats, row-major, symmetric with a zero diagonal
+ *          (not checked) and integer entries |J_ij| <= 127; any other entry
+ *          makes every e_int entry INT32_MIN.
+ *   x    : device, r*n floats, replica-major positions (x[r*n + i]).
+ *   e_int: device, r int32; INT32_MIN where the energy does not fit in int32.
+ * Its scratch memory (per-replica sums, 512 KiB) is one static device array
+ * per GPU, held until the process ends; every call clears the part it uses
+ * before using it.  Calls that overlap on one GPU (on different streams)
+ * share that array and race.  Nothing is allocated or freed and no
+ * allocating library routine is called.  Asynchronous on hip_stream (NULL =
+ * null stream). */
+si_status spring_ising_energy_noalloc(int32_t n, int32_t r, const float *J, const float *x,
+                                      int32_t *e_int, void *hip_stream);
+
 /* Best state seen along the trajectory (the paper samples the spins of the
  * final state, Methods; tracking the lowest energy met on the way, Fig. 4,
  * keeps the best of them): evaluate the Eq. (1) energy of the current spins

@@ -228,6 +228,14 @@ hipError_t launch_unpack_spins(const int8_t *src, int32_t n, int32_t r, int8_t *
 hipError_t launch_pack_field(const float *h, int32_t n, float *hf, int8_t *h8,
                              int32_t n_pad, int32_t *flags, hipStream_t s);
 
+// Allocation-free exact energy: scratch is a static device array per GPU
+// (its device address looked up once per device), at most noalloc_r_max()
+// replicas.
+int32_t noalloc_r_max();
+hipError_t noalloc_scratch_ptr(int device, void **ptr);
+hipError_t launch_noalloc_energy(const float *J, const float *x, int32_t n, int32_t r,
+                                 int32_t *e_int, void *scratch_ptr, hipStream_t s);
+
 // flags[0]: asymmetric, [1]: nonzero diagonal, [2]: non-finite,
 // [3]: non-integer or |J|>127, [4]: not FP8-e4m3 exact, [5]: not BF16 exact
 hipError_t launch_validate(const float *J, int32_t n, int32_t *flags, hipStream_t s);

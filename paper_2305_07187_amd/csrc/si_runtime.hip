@@ -399,6 +399,25 @@ const char *spring_ising_last_error(void) { return g_last_error.c_str(); }
 
 const char *spring_ising_build_id(void) { return k_build_id + 12; }
 
+si_status spring_ising_energy_noalloc(int32_t n, int32_t r, const float *J, const float *x,
+                                      int32_t *e_int, void *hip_stream) {
+  if (n < 1 || n > 65536)
+    return fail(SI_ERR_INVALID, "energy_noalloc: n=%d outside 1..65536", n);
+  if (r < 1 || r > noalloc_r_max())
+    return fail(SI_ERR_INVALID, "energy_noalloc: r=%d outside 1..%d (the static scratch holds "
+                "%d replicas)", r, noalloc_r_max(), noalloc_r_max());
+  if (!is_device_ptr(J) || !is_device_ptr(x) || !is_device_ptr(e_int))
+    return fail(SI_ERR_INVALID, "energy_noalloc: J, x and e_int must be device pointers");
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  void *sc = nullptr;
+  if (e == hipSuccess) e = noalloc_scratch_ptr(dev, &sc);
+  if (e == hipSuccess)
+    e = launch_noalloc_energy(J, x, n, r, e_int, sc, static_cast<hipStream_t>(hip_stream));
+  if (e != hipSuccess) return fail(SI_ERR_HIP, "energy_noalloc: %s", hipGetErrorString(e));
+  return SI_OK;
+}
+
 si_status spring_ising_debug_inject_hip_error(si_ctx *c, int32_t n) {
   SI_USABLE(c);
   if (n < 0) return fail(SI_ERR_INVALID, "debug_inject_hip_error: n=%d < 0", n);
@@ -456,6 +475,11 @@ si_status spring_ising_init(si_ctx **out, int32_t n, int32_t r, const float *J, 
   } while (0)
   INIT_HIP(hipGetDevice(&c->device));
   INIT_HIP(hipDeviceGetAttribute(&c->num_cus, hipDeviceAttributeMultiprocessorCount, c->device));
+  {
+    void *sc = nullptr;  // set-up of the allocation-free entry point on this device
+    INIT_HIP(noalloc_scratch_ptr(c->device, &sc));
+  }
+
   // validation of J: one host round trip
   INIT_HIP(c->alloc(&c->flags, 8));
   INIT_HIP(launch_zero_i32(c->flags, 8, c->stream));

@@ -100,6 +100,7 @@ _SIGNATURES = {
     "spring_ising_init_batch": [ctypes.POINTER(_P), _I, _P, _I, _P, _P, _P,
                                 ctypes.POINTER(si_params), _P],
     "spring_ising_debug_inject_hip_error": [_P, _I],
+    "spring_ising_energy_noalloc": [_I, _I, _P, _P, _P, _P],
     "spring_ising_get_energy_trace": [_P, _P, ctypes.POINTER(_I)],
     "spring_ising_destroy": [_P],
 }
@@ -143,6 +144,15 @@ def last_error() -> str:
 
 def spring_ising_build_id() -> str:
     return load_library().spring_ising_build_id().decode()
+
+
+def spring_ising_energy_noalloc(J, x, e_int, stream=None):
+    """J: [N, N] float32, x: [R, N] float32, e_int: [R] int32 CUDA tensors."""
+    import torch
+    n, r = int(J.shape[0]), int(x.shape[0])
+    _check(load_library().spring_ising_energy_noalloc(
+        n, r, _ptr(J, torch.float32, n * n, "J"), _ptr(x, torch.float32, n * r, "x"),
+        _ptr(e_int, torch.int32, r, "e_int"), stream if stream is not None else _stream()))
 
 
 def spring_ising_get_energy_trace(ctx, e=None):
