@@ -48,19 +48,19 @@ __device__ __forceinline__ uint32_t epi_bf16(float x) {
 
 // The BM (spins) x BN (replicas) output tile in LDS, replica-major: element
 // (row i, column j) at t[j * LD + i].  Rows are padded by four floats so that
-// the 16-byte writes of 16 consecutive columns fall on distinct banks.
-template <int BM, int BN, int NT>
+// the 16-byte writes of 16 consecutive columns fall on distinct banks.  The
+// NT threads from thread T0 on share the tile's chunks.
+template <int BM, int BN, int NT, int T0 = 0>
 struct EpiTile {
   static constexpr int LD = BM + 4;
   static constexpr int BYTES = BN * LD * 4;
   static constexpr int CHUNKS = BM * BN / 4;  // 16-byte chunks of the tile
   static constexpr int CPT = CHUNKS / NT;     // chunks per thread
   static_assert(BM % 4 == 0 && CHUNKS % NT == 0, "epilogue chunks");
+  static __device__ __forceinline__ int tid() { return (int)threadIdx.x - T0; }
   // chunk c of this thread: tile-local column (replica) and first row (spin)
-  static __device__ __forceinline__ int col(int c) { return (c * NT + (int)threadIdx.x) / (BM / 4); }
-  static __device__ __forceinline__ int row(int c) {
-    return ((c * NT + (int)threadIdx.x) % (BM / 4)) * 4;
-  }
+  static __device__ __forceinline__ int col(int c) { return (c * NT + tid()) / (BM / 4); }
+  static __device__ __forceinline__ int row(int c) { return ((c * NT + tid()) % (BM / 4)) * 4; }
 };
 
 // What the update of one tile reads and writes.
@@ -145,6 +145,74 @@ __device__ __forceinline__ void epi_apply(const float *t, const EpiArgs &e,
           uintx2{b2[0] | (b2[1] << 16), b2[2] | (b2[3] << 16)};
     }
     if (QP == 0 && e.mask_out) *reinterpret_cast<uint32_t *>(e.mask_out + off) = mk;
+  }
+}
+
+// The paper-order update in two halves.  q' = clamp(q + (Delta/m) p) needs
+// no coupling term, so epi_apply_q computes it, with its BF16 plane(s), and
+// stores it while the product of the same tile still runs; epi_apply_p
+// applies the coupling once F is in LDS.  Each value is computed with the
+// same operations as spring_update (bit-identical results).
+template <class T, int QP>
+__device__ __forceinline__ void epi_apply_q(const EpiArgs &e, const floatx4 (&q4)[T::CPT],
+                                            const floatx4 (&p4)[T::CPT]) {
+  const float cdt = e.dt * e.inv_m;
+#pragma unroll
+  for (int c = 0; c < T::CPT; ++c) {
+    const size_t off = (size_t)(e.n0 + T::col(c)) * e.ld + e.m0 + T::row(c);
+    floatx4 qn;
+    uint32_t b0[4], b1[4], b2[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const float u = fmaf(cdt, p4[c][v], q4[c][v]);
+      qn[v] = fminf(fmaxf(u, -e.qmax), e.qmax);
+      if (QP >= 1) b0[v] = epi_bf16(qn[v]);
+      if (QP == 3) {
+        const float r1 = qn[v] - __uint_as_float(b0[v] << 16);  // exact
+        b1[v] = epi_bf16(r1);
+        const float r2 = r1 - __uint_as_float(b1[v] << 16);  // exact
+        b2[v] = epi_bf16(r2);
+      }
+    }
+    *reinterpret_cast<floatx4 *>(e.q_out + off) = qn;
+    if (QP >= 1)
+      *reinterpret_cast<uintx2 *>(e.qb_out + off) =
+          uintx2{b0[0] | (b0[1] << 16), b0[2] | (b0[3] << 16)};
+    if (QP == 3) {
+      *reinterpret_cast<uintx2 *>(e.qb_out + e.plane_stride + off) =
+          uintx2{b1[0] | (b1[1] << 16), b1[2] | (b1[3] << 16)};
+      *reinterpret_cast<uintx2 *>(e.qb_out + 2 * e.plane_stride + off) =
+          uintx2{b2[0] | (b2[1] << 16), b2[2] | (b2[3] << 16)};
+    }
+  }
+}
+
+template <class T, int WALL>
+__device__ __forceinline__ void epi_apply_p(const float *t, const EpiArgs &e,
+                                            const floatx4 (&q4)[T::CPT],
+                                            const floatx4 (&p4)[T::CPT]) {
+#pragma unroll
+  for (int c = 0; c < T::CPT; ++c) {
+    const int col = T::col(c), row = T::row(c);
+    const size_t off = (size_t)(e.n0 + col) * e.ld + e.m0 + row;
+    const floatx4 f = *reinterpret_cast<const floatx4 *>(t + col * T::LD + row);
+    floatx4 h4 = {0.f, 0.f, 0.f, 0.f};
+    if (e.h) h4 = *reinterpret_cast<const floatx4 *>(e.h + e.m0 + row);
+    floatx4 pn;
+    uint32_t mk = 0;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const float force = fmaf(e.zeta, f[v] + h4[v], -e.k * q4[c][v]);
+      const float vv = fmaf(e.dt, force, p4[c][v]);
+      pn[v] = fminf(fmaxf(vv, -e.pmax), e.pmax);
+      if (WALL == SI_WALL_INELASTIC || e.mask_out) {
+        const float uu = fmaf(e.dt * e.inv_m, p4[c][v], q4[c][v]);
+        if (WALL == SI_WALL_INELASTIC && fabsf(uu) > e.qmax) pn[v] = 0.f;
+        mk |= ((fabsf(uu) <= e.qmax ? 1u : 0u) | (fabsf(vv) <= e.pmax ? 2u : 0u)) << (8 * v);
+      }
+    }
+    *reinterpret_cast<floatx4 *>(e.p_out + off) = pn;
+    if (e.mask_out) *reinterpret_cast<uint32_t *>(e.mask_out + off) = mk;
   }
 }
 

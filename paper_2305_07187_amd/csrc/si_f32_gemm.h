@@ -30,15 +30,9 @@ struct MfmaF32<32> {
   }
 };
 
-template <int BM_, int BN_, int WM_, int WN_, int MB_, int BK_, int STAGES_ = 0, int KS_ = 1,
-          int PIPE_ = 0>
+template <int BM_, int BN_, int WM_, int WN_, int MB_, int BK_, int STAGES_ = 0, int KS_ = 1>
 struct F32Cfg {
   static constexpr int BM = BM_, BN = BN_, WM = WM_, WN = WN_, MB = MB_, BK = BK_;
-  // PIPE = 1 (direct-to-LDS ring only): the barrier that hands over slab
-  // k + 1 comes before the last contraction step of slab k, so that the
-  // first fragments of slab k + 1 are read while the last matrix-core
-  // operations of slab k run (no fragment-read latency after each barrier).
-  static constexpr int PIPE = PIPE_;
   // KS independent accumulators per output block, alternating over the
   // four MFMAs of each contraction step (shorter dependency chains) and
   // added at the end (direct-to-LDS pipeline only).
@@ -74,13 +68,6 @@ typedef __attribute__((address_space(1))) const void gbl_void_t;
 template <int N>
 __device__ __forceinline__ void wait_vm_barrier() {
   asm volatile("s_waitcnt vmcnt(%0)\n\ts_barrier" ::"n"(N) : "memory");
-}
-
-// The same, also waiting for this wave's LDS reads: the slot they read may
-// be refilled once every wave has passed the barrier.
-template <int N>
-__device__ __forceinline__ void wait_vm_lgkm_barrier() {
-  asm volatile("s_waitcnt vmcnt(%0) lgkmcnt(0)\n\ts_barrier" ::"n"(N) : "memory");
 }
 
 // Direct-to-LDS pipeline.  Each slab row of BK floats is stored unpadded;
@@ -152,68 +139,10 @@ __device__ __forceinline__ void f32_mainloop_dma(const float *__restrict__ A,
   for (int s = 0; s < S - 1; ++s)
     if (s < nk) issue(s, s);
   const int ra = wy * C::WTM + lrow, rb = wx * C::WTN + lrow;  // fragment rows (i = j = 0)
-  // fragments of contraction step kk of the slab at st
-  auto frag_at = [&](const float *st, int kk, floatx4 (&fa)[C::TM], floatx4 (&fb)[C::TN]) {
-    const int ch = (kk + lk) >> 2;
-#pragma unroll
-    for (int i = 0; i < C::TM; ++i) {
-      const int r = ra + i * C::MB;
-      fa[i] = *reinterpret_cast<const floatx4 *>(st + r * C::BK + ((ch ^ lds_swz<CH>(r)) << 2));
-    }
-#pragma unroll
-    for (int j = 0; j < C::TN; ++j) {
-      const int r = rb + j * C::MB;
-      fb[j] = *reinterpret_cast<const floatx4 *>(st + (C::BM + r) * C::BK + ((ch ^ lds_swz<CH>(r)) << 2));
-    }
-  };
-  if constexpr (C::PIPE) {
-    constexpr int NKS = C::BK / C::KSTEP;
-    floatx4 a[2][C::TM], b[2][C::TN];
-    int rd = 0, wr = S - 1;
-    if (nk > 0) {
-      if (S - 1 < nk) {
-        wait_vm_barrier<(S - 2) * L>();
-        issue(S - 1, wr);
-      } else {
-        wait_vm_barrier<0>();
-      }
-      wr = wr + 1 == S ? 0 : wr + 1;
-      frag_at(smem, 0, a[0], b[0]);
-    }
-    for (int kt = 0; kt < nk; ++kt) {
-      const float *st = smem + rd * SLAB;
-#pragma unroll
-      for (int ks = 0; ks < NKS; ++ks) {
-        const int cur = ks & 1;
-        if (ks + 1 < NKS) {
-          frag_at(st, (ks + 1) * C::KSTEP, a[cur ^ 1], b[cur ^ 1]);
-        } else if (kt + 1 < nk) {
-          // every wave has its fragments of slab kt (lgkmcnt) and slab kt + 1
-          // has landed: slot rd may be refilled with slab kt + S
-          if (kt + S < nk) {
-            wait_vm_lgkm_barrier<(S - 2) * L>();
-            issue(kt + S, wr);
-          } else {
-            wait_vm_lgkm_barrier<0>();
-          }
-          wr = wr + 1 == S ? 0 : wr + 1;
-          rd = rd + 1 == S ? 0 : rd + 1;
-          frag_at(smem + rd * SLAB, 0, a[cur ^ 1], b[cur ^ 1]);
-        }
-#pragma unroll
-        for (int s = 0; s < 4; ++s)
-#pragma unroll
-          for (int i = 0; i < C::TM; ++i)
-#pragma unroll
-            for (int j = 0; j < C::TN; ++j)
-              part[i][j][s % C::KS] = C::M::mma(a[cur][i][s], b[cur][j][s], part[i][j][s % C::KS]);
-      }
-    }
-  }
   // ring slots read and written this iteration (kt % S and (kt + S - 1) % S,
   // kept as counters so that no division runs in the loop)
   int rd = 0, wr = S - 1;
-  for (int kt = 0; kt < (C::PIPE ? 0 : nk); ++kt) {
+  for (int kt = 0; kt < nk; ++kt) {
     if (kt + S - 1 < nk) {
       wait_vm_barrier<(S - 2) * L>();
       issue(kt + S - 1, wr);
@@ -369,44 +298,41 @@ __device__ __forceinline__ int acc_row(int lane, int v) {
 
 
 // Tile table: id, BM, BN, waves (WM x WN), MFMA block edge, slab depth BK,
-// LDS stages (0: register-staged double buffer; >= 3: direct-to-LDS ring),
-// accumulator chains, and the pipelined ring (PIPE, F32Cfg).
+// LDS stages (0: register-staged double buffer; >= 3: direct-to-LDS ring).
 #define SI_F32_TILES(X)                \
-  X(1, 64, 128, 2, 2, 32, 32, 0, 1, 0)    \
-  X(2, 64, 64, 2, 2, 32, 32, 0, 1, 0)        \
-  X(3, 32, 32, 2, 2, 16, 32, 0, 1, 0)        \
-  X(4, 128, 64, 2, 2, 32, 32, 0, 1, 0)       \
-  X(5, 128, 128, 2, 2, 32, 32, 0, 1, 0)      \
-  X(6, 32, 64, 2, 2, 16, 32, 0, 1, 0)        \
-  X(7, 64, 128, 2, 2, 32, 64, 0, 1, 0)       \
-  X(8, 64, 128, 2, 4, 32, 32, 0, 1, 0)       \
-  X(9, 64, 64, 2, 2, 32, 64, 0, 1, 0)        \
-  X(10, 64, 128, 2, 2, 16, 32, 0, 1, 0)      \
-  X(11, 128, 128, 2, 4, 32, 32, 0, 1, 0)     \
-  X(12, 64, 64, 2, 2, 16, 32, 0, 1, 0)       \
-  X(13, 64, 64, 2, 2, 32, 32, 3, 1, 0)       \
-  X(14, 64, 64, 2, 2, 32, 32, 4, 1, 0)       \
-  X(15, 64, 64, 2, 2, 32, 64, 3, 1, 0)       \
-  X(16, 64, 128, 2, 2, 32, 32, 4, 1, 0)      \
-  X(17, 64, 64, 2, 2, 32, 32, 6, 1, 0)       \
-  X(18, 128, 64, 2, 2, 32, 32, 4, 1, 0)      \
-  X(19, 64, 64, 2, 2, 32, 32, 4, 2, 0)    \
-  X(20, 64, 64, 2, 2, 32, 32, 4, 4, 0)    \
-  X(21, 64, 64, 2, 1, 32, 32, 4, 1, 0)    \
-  X(22, 64, 64, 2, 1, 32, 32, 4, 2, 0)    \
-  X(23, 64, 64, 2, 2, 32, 64, 3, 2, 0)    \
-  X(24, 64, 128, 2, 2, 32, 32, 4, 2, 0)   \
-  X(25, 128, 64, 4, 2, 32, 32, 0, 1, 0)   \
-  X(26, 128, 64, 4, 2, 32, 32, 4, 1, 0)   \
-  X(27, 64, 128, 2, 4, 32, 32, 4, 1, 0)   \
-  X(28, 128, 64, 4, 2, 32, 64, 3, 1, 0)   \
-  X(29, 128, 128, 4, 4, 32, 32, 0, 1, 0)  \
-  X(30, 128, 64, 4, 2, 32, 32, 6, 1, 0)   \
-  X(31, 128, 64, 4, 2, 32, 32, 4, 2, 0)   \
-  X(32, 64, 128, 2, 4, 32, 32, 6, 1, 0)   \
-  X(33, 128, 64, 4, 2, 32, 32, 5, 1, 0)   \
-  X(34, 128, 64, 4, 2, 32, 32, 3, 1, 0)  \
-  X(35, 64, 128, 2, 4, 32, 32, 4, 1, 1)  \
-  X(36, 128, 64, 4, 2, 32, 32, 4, 1, 1)
+  X(1, 64, 128, 2, 2, 32, 32, 0, 1)    \
+  X(2, 64, 64, 2, 2, 32, 32, 0, 1)        \
+  X(3, 32, 32, 2, 2, 16, 32, 0, 1)        \
+  X(4, 128, 64, 2, 2, 32, 32, 0, 1)       \
+  X(5, 128, 128, 2, 2, 32, 32, 0, 1)      \
+  X(6, 32, 64, 2, 2, 16, 32, 0, 1)        \
+  X(7, 64, 128, 2, 2, 32, 64, 0, 1)       \
+  X(8, 64, 128, 2, 4, 32, 32, 0, 1)       \
+  X(9, 64, 64, 2, 2, 32, 64, 0, 1)        \
+  X(10, 64, 128, 2, 2, 16, 32, 0, 1)      \
+  X(11, 128, 128, 2, 4, 32, 32, 0, 1)     \
+  X(12, 64, 64, 2, 2, 16, 32, 0, 1)       \
+  X(13, 64, 64, 2, 2, 32, 32, 3, 1)       \
+  X(14, 64, 64, 2, 2, 32, 32, 4, 1)       \
+  X(15, 64, 64, 2, 2, 32, 64, 3, 1)       \
+  X(16, 64, 128, 2, 2, 32, 32, 4, 1)      \
+  X(17, 64, 64, 2, 2, 32, 32, 6, 1)       \
+  X(18, 128, 64, 2, 2, 32, 32, 4, 1)      \
+  X(19, 64, 64, 2, 2, 32, 32, 4, 2)    \
+  X(20, 64, 64, 2, 2, 32, 32, 4, 4)    \
+  X(21, 64, 64, 2, 1, 32, 32, 4, 1)    \
+  X(22, 64, 64, 2, 1, 32, 32, 4, 2)    \
+  X(23, 64, 64, 2, 2, 32, 64, 3, 2)    \
+  X(24, 64, 128, 2, 2, 32, 32, 4, 2)   \
+  X(25, 128, 64, 4, 2, 32, 32, 0, 1)   \
+  X(26, 128, 64, 4, 2, 32, 32, 4, 1)   \
+  X(27, 64, 128, 2, 4, 32, 32, 4, 1)   \
+  X(28, 128, 64, 4, 2, 32, 64, 3, 1)   \
+  X(29, 128, 128, 4, 4, 32, 32, 0, 1)  \
+  X(30, 128, 64, 4, 2, 32, 32, 6, 1)   \
+  X(31, 128, 64, 4, 2, 32, 32, 4, 2)   \
+  X(32, 64, 128, 2, 4, 32, 32, 6, 1)   \
+  X(33, 128, 64, 4, 2, 32, 32, 5, 1)   \
+  X(34, 128, 64, 4, 2, 32, 32, 3, 1)
 
 }  // namespace si

@@ -12,7 +12,7 @@ namespace si {
 // Tile ids of the FP32 step kernel (see the tile table in si_step_f32.hip);
 // 0 selects automatically.
 constexpr int32_t TILE_AUTO = 0;
-constexpr int32_t TILE_F32_LAST = 36;
+constexpr int32_t TILE_F32_LAST = 34;
 
 // Work-groups of a launch are dispatched to the eight XCDs in turn (group b
 // runs on XCD b % 8), and each XCD has its own L2.  xcd_tile() renumbers the
@@ -109,7 +109,7 @@ hipError_t launch_step_batch_f32(const StepArgs &a, const BatchDesc *descs, cons
                                  int32_t n_items, int32_t cur, hipStream_t s);
 
 // Step on the BF16 matrix cores (precision forms).
-constexpr int32_t TILE_BF16_LAST = 34;
+constexpr int32_t TILE_BF16_LAST = 33;
 TileShape tile_shape_bf16(int32_t tile);
 struct BStepArgs {
   const void *Ja;         // J plane: bf16 or fp8 [n_pad][n_pad]

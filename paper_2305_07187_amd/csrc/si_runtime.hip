@@ -300,10 +300,13 @@ static int32_t choose_tile_bf16(int32_t n, int32_t r, int num_cus, int32_t preci
   // tiles as the fallback for small problems.  Tiles 26 and 28 are the
   // pipelined twins (bit-identical results) of the three-plane 128x64 tile
   // and the hi + lo 128x256 tile: 32.1 -> 30.5 us at N=2000, R=1024 and
-  // 482 -> 470 us at N=8000, R=2048.
-  static const int32_t pref_bf16j[] = {16, 18, 23, 8, 7, 11, 10, 1, 2, 3};
-  static const int32_t pref_fp8j[] = {19, 14, 23, 9, 13, 1, 6, 2, 3};
-  static const int32_t pref_hilo[] = {28, 18, 7, 10, 11, 1, 2, 3};
+  // 482 -> 470 us at N=8000, R=2048.  Tiles 32 and 33 add state waves to
+  // the eight-wave 128x64 tiles (single-plane forms at N=2000, R=1024: FP8
+  // J 18.2 -> 17.1 us, BF16 J 19.4 -> 18.4 us; hi + lo 26.3 -> 25.6 us
+  // against the 64x64 tile).
+  static const int32_t pref_bf16j[] = {16, 18, 32, 8, 7, 11, 10, 1, 2, 3};
+  static const int32_t pref_fp8j[] = {19, 14, 32, 9, 13, 1, 6, 2, 3};
+  static const int32_t pref_hilo[] = {28, 18, 33, 7, 10, 11, 1, 2, 3};
   static const int32_t pref_exact[] = {21, 22, 26, 11, 8, 7, 1, 2, 3};
 #define SI_PREF(a) order = a, count = (int)(sizeof a / sizeof a[0])
   const int32_t *order;

@@ -204,7 +204,7 @@ static hipError_t split_step(const StepArgs &a, hipStream_t s) {
 
 bool tile_has_split(int32_t tile) {
   switch (tile) {
-#define SI_HS(id, bm, bn, wm, wn, mb, bk, st, ks, pp) \
+#define SI_HS(id, bm, bn, wm, wn, mb, bk, st, ks) \
   case id:                                       \
     return SI_HAS_SPLIT(id);
     SI_F32_TILES(SI_HS)
@@ -215,10 +215,10 @@ bool tile_has_split(int32_t tile) {
 
 hipError_t launch_step_f32_split(int32_t tile, const StepArgs &a, hipStream_t s) {
   switch (tile) {
-#define SI_SL(id, bm, bn, wm, wn, mb, bk, st, ks, pp)                              \
+#define SI_SL(id, bm, bn, wm, wn, mb, bk, st, ks)                              \
   case id:                                                                    \
     if constexpr (SI_HAS_SPLIT(id))                                           \
-      return split_step<F32Cfg<bm, bn, wm, wn, mb, bk, st, ks, pp>>(a, s);        \
+      return split_step<F32Cfg<bm, bn, wm, wn, mb, bk, st, ks>>(a, s);        \
     else                                                                      \
       return hipErrorInvalidValue;
     SI_F32_TILES(SI_SL)

@@ -207,15 +207,23 @@ __device__ __forceinline__ void wait_vm_barrier_b() {
   asm volatile("s_waitcnt vmcnt(%0)\n\ts_barrier" ::"n"(N) : "memory");
 }
 
-// Also waits for this wave's LDS reads (the slot they read may be refilled
-// once every wave has passed the barrier).
+// Pipelined ring: the counter wait goes through the builtin, which the
+// compiler's wait insertion accounts for; the barrier stays in asm with a
+// memory clobber.  The _lgkm form also waits for this wave's LDS reads (the
+// slot they read may be refilled once every wave has passed the barrier).
+template <int N>
+__device__ __forceinline__ void wait_vm_barrier_pb() {
+  __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
+  asm volatile("s_barrier" ::: "memory");
+}
 template <int N>
 __device__ __forceinline__ void wait_vm_lgkm_barrier_b() {
-  asm volatile("s_waitcnt vmcnt(%0) lgkmcnt(0)\n\ts_barrier" ::"n"(N) : "memory");
+  __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4));
+  asm volatile("s_barrier" ::: "memory");
 }
 
 template <int BM_, int BN_, int WM_, int WN_, int BK_, int JFMT_, int QP_, int STAGES_,
-          int PIPE_ = 0>
+          int PIPE_ = 0, int SW_ = 0>
 struct Bf16DmaCfg {
   static constexpr int BM = BM_, BN = BN_, WM = WM_, WN = WN_, BK = BK_;
   static constexpr int JFMT = JFMT_, QP = QP_, STAGES = STAGES_;
@@ -224,12 +232,16 @@ struct Bf16DmaCfg {
   // that the first fragments of slab k + 1 are read while the last
   // matrix-core operations of slab k run.
   static constexpr int PIPE = PIPE_;
+  // SW > 0 (pipelined ring only): SW state waves beside the NW matrix waves
+  // own the tile's state (see bf16_dma_tile_sw).
+  static constexpr int SW = SW_;
   static constexpr int JP = JFMT == 2 ? 2 : 1;
   static constexpr int EA = JFMT == 1 ? 1 : 2;  // bytes per J element in LDS
   static constexpr int MB = 32;
   static constexpr int WTM = BM / WM, WTN = BN / WN;
   static constexpr int TM = WTM / MB, TN = WTN / MB;
   static constexpr int NT = 64 * WM * WN, NW = NT / 64;
+  static constexpr int NTT = NT + 64 * SW;  // threads of the workgroup
   static constexpr int ROWA = BK * EA, ROWB = BK * 2;  // bytes per row
   static constexpr int CHA = ROWA / 16, CHB = ROWB / 16;
   static constexpr int RPDA = 64 / CHA, RPDB = 64 / CHB;  // rows per wave-wide load
@@ -245,6 +257,7 @@ struct Bf16DmaCfg {
                 "direct-to-LDS slab split");
   static_assert(TM >= 1 && TN >= 1 && BK % 32 == 0, "tile");
   static_assert(STAGES >= 2 && (STAGES - 2) * L <= 63, "pipeline depth");
+  static_assert(SW == 0 || PIPE, "state waves need the pipelined ring");
 };
 
 // 8 FP8 e4m3 values (two words) -> 8 BF16 (exact: e4m3 has 4 significant
@@ -260,8 +273,7 @@ __device__ __forceinline__ bf16x8 fp8x8_to_bf16x8(uint32_t w0, uint32_t w1) {
 
 template <class C>
 __device__ __forceinline__ void bf16_mainloop_dma(const BStepArgs &a, int m0, int n0,
-                                                  floatx16 (&acc)[C::TM][C::TN],
-                                                  uint8_t *smem) {
+                                                  floatx16 (&acc)[C::TM][C::TN], uint8_t *smem) {
   constexpr int S = C::STAGES;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wy = wave / C::WN, wx = wave % C::WN;
@@ -325,9 +337,11 @@ __device__ __forceinline__ void bf16_mainloop_dma(const BStepArgs &a, int m0, in
   };
 
   const int nk = a.n_pad / C::BK;
+  if constexpr (!C::PIPE) {
 #pragma unroll
-  for (int s = 0; s < S - 1; ++s)
-    if (s < nk) issue(s, s);
+    for (int s = 0; s < S - 1; ++s)
+      if (s < nk) issue(s, s);
+  }
   // Raw fragments of one 32-deep step: FP8 J as one 16-byte chunk per row
   // block (both halves of the step), BF16 planes as two 16-byte chunks.
   constexpr int AC = C::JFMT == 1 ? 1 : 2;
@@ -401,11 +415,19 @@ __device__ __forceinline__ void bf16_mainloop_dma(const BStepArgs &a, int m0, in
     Frag fr[2];
     int rd = 0, wr = S - 1;
     if (nk > 0) {
+      // prologue: S - 1 slabs in flight, slab 0 awaited, slab S - 1 issued
+      // (on the long path every slab is issued unconditionally, so that the
+      // compiler's count of the loads issued before them is exact)
       if (S - 1 < nk) {
-        wait_vm_barrier_b<(S - 2) * C::L>();
+#pragma unroll
+        for (int s = 0; s < S - 1; ++s) issue(s, s);
+        wait_vm_barrier_pb<(S - 2) * C::L>();
         issue(S - 1, wr);
       } else {
-        wait_vm_barrier_b<0>();
+#pragma unroll
+        for (int s = 0; s < S - 1; ++s)
+          if (s < nk) issue(s, s);
+        wait_vm_barrier_pb<0>();
       }
       wr = wr + 1 == S ? 0 : wr + 1;
       read_frag(smem, 0, fr[0]);
@@ -557,11 +579,73 @@ __device__ __forceinline__ void bf16_dma_tile(const BStepArgs &a, int m0, int n0
   bf16_update<T, C::QP, ORDER, WALL>(a, m0, n0, tile, q4, p4);
 }
 
+// One tile with state waves (C::SW > 0).  The matrix waves run the ring and
+// leave F in LDS; they never touch the state.  The state waves load the
+// tile's q and p, and in the paper order (q' needs no coupling term) store
+// q' and its BF16 plane(s) while the product runs, then apply p' from F.
+// Their vector-memory counter holds only their own loads and stores, so the
+// compiler's waits for them never drain the matrix waves' ring.  Both roles
+// pass the same barriers: the ring's nk + 1 and the one before the update.
+// The role is taken from readfirstlane, so the branch on it is a scalar
+// branch that each wave takes whole.
+__device__ __forceinline__ void bare_barrier() { asm volatile("s_barrier" ::: "memory"); }
+
 template <class C, int ORDER, int WALL>
-__global__ __launch_bounds__(C::NT) void step_bf16_dma_kernel(BStepArgs a) {
+__device__ __forceinline__ void bf16_dma_tile_sw(const BStepArgs &a, int m0, int n0,
+                                                 uint8_t *smem) {
+  using TS = EpiTile<C::BM, C::BN, 64 * C::SW, C::NT>;
+  static_assert(TS::BYTES <= C::LDS_BYTES, "the update tile fits in the main loop's LDS");
+  const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+  float *tile = reinterpret_cast<float *>(smem);
+  if (wave < C::NW) {
+    floatx16 acc[C::TM][C::TN];
+    bf16_mainloop_dma<C>(a, m0, n0, acc, smem);  // nk + 1 barriers
+    bf16_put<C>(tile, TS::LD, acc);
+    __syncthreads();
+    return;
+  }
+  EpiArgs e;
+  e.q_in = a.q_in;
+  e.p_in = a.p_in;
+  e.h = a.h;
+  e.q_out = a.q_out;
+  e.p_out = a.p_out;
+  e.qb_out = a.qb_out;
+  e.plane_stride = a.plane_stride;
+  e.mask_out = nullptr;
+  e.ld = a.ld;
+  e.m0 = m0;
+  e.n0 = n0;
+  e.dt = a.dt[a.t];
+  e.zeta = a.zeta[a.t];
+  e.k = a.k;
+  e.inv_m = a.inv_m;
+  e.qmax = a.qmax;
+  e.pmax = a.pmax;
+  floatx4 q4[TS::CPT], p4[TS::CPT];
+  epi_load<TS>(e, q4, p4);
+  const int nk = a.n_pad / C::BK;
+  if (nk > 0) {
+    bare_barrier();  // the ring's prologue barrier
+    if constexpr (ORDER == SI_ORDER_PAPER) epi_apply_q<TS, C::QP>(e, q4, p4);
+    for (int i = 1; i < nk; ++i) bare_barrier();  // the ring's slab hand-overs
+  }
+  bare_barrier();  // the ring's final barrier
+  __syncthreads();
+  if constexpr (ORDER == SI_ORDER_PAPER)
+    epi_apply_p<TS, WALL>(tile, e, q4, p4);
+  else
+    epi_apply<TS, ORDER, WALL, C::QP>(tile, e, q4, p4);
+}
+
+template <class C, int ORDER, int WALL>
+__global__ __launch_bounds__(C::NTT) void step_bf16_dma_kernel(BStepArgs a) {
   __shared__ __attribute__((aligned(16))) uint8_t smem[C::LDS_BYTES];
   const int t = xcd_tile(blockIdx.x, gridDim.x), ncol = a.r_pad / C::BN;
-  bf16_dma_tile<C, ORDER, WALL>(a, (t / ncol) * C::BM, (t % ncol) * C::BN, smem);
+  if constexpr (C::SW > 0)
+    bf16_dma_tile_sw<C, ORDER, WALL>(a, (t / ncol) * C::BM, (t % ncol) * C::BN, smem);
+  else
+    bf16_dma_tile<C, ORDER, WALL>(a, (t / ncol) * C::BM, (t % ncol) * C::BN, smem);
 }
 
 // Batched precision form: one launch advances every instance by one step.
@@ -626,7 +710,7 @@ hipError_t launch_step_batch_bf16(const BStepArgs &base, const BBatchDesc *descs
 template <class C>
 static hipError_t launch_bd(const BStepArgs &a, hipStream_t s) {
   if (a.n_pad % C::BM || a.r_pad % C::BN || a.n_pad % C::BK) return hipErrorInvalidValue;
-  dim3 grid((a.n_pad / C::BM) * (a.r_pad / C::BN)), block(C::NT);
+  dim3 grid((a.n_pad / C::BM) * (a.r_pad / C::BN)), block(C::NTT);
   switch (a.order * 2 + a.wall) {
     case 0: step_bf16_dma_kernel<C, SI_ORDER_PAPER, SI_WALL_CLAMP><<<grid, block, 0, s>>>(a); break;
     case 1: step_bf16_dma_kernel<C, SI_ORDER_PAPER, SI_WALL_INELASTIC><<<grid, block, 0, s>>>(a); break;
@@ -677,19 +761,19 @@ static hipError_t launch_bd(const BStepArgs &a, hipStream_t s) {
   X(26, 128, 64, 4, 2, 64, 3, 1)   \
   X(27, 128, 128, 4, 2, 128, 3, 1) \
   X(28, 128, 256, 2, 4, 64, 2, 1)  \
-  X(29, 64, 64, 2, 2, 64, 3, 1)    \
-  X(30, 128, 64, 4, 2, 128, 4, 1)  \
-  X(31, 128, 64, 4, 2, 64, 4, 1)   \
-  X(32, 128, 256, 2, 4, 64, 3, 1)  \
-  X(33, 256, 128, 4, 2, 64, 2, 1)  \
-  X(34, 128, 128, 2, 4, 64, 2, 1)
+  X(29, 128, 256, 2, 4, 64, 3, 1)  \
+  X(30, 256, 128, 4, 2, 64, 2, 1)  \
+  X(31, 128, 128, 2, 4, 64, 2, 1)  \
+  X(32, 128, 64, 4, 2, 128, 3, 2)  \
+  X(33, 128, 64, 4, 2, 64, 3, 2)
 
 TileShape tile_shape_bf16(int32_t tile) {
   switch (tile) {
 #define SI_SHAPE(id, bm, bn, wm, wn, bk, st, pp) \
   case id:                                   \
     return {bm, bn,                          \
-            pp ? "step_bf16_" #bm "x" #bn "_w" #wm "x" #wn "_k" #bk "_s" #st "_p1" \
+            pp == 2 ? "step_bf16_" #bm "x" #bn "_w" #wm "x" #wn "_k" #bk "_s" #st "_p2" \
+            : pp    ? "step_bf16_" #bm "x" #bn "_w" #wm "x" #wn "_k" #bk "_s" #st "_p1" \
                : "step_bf16_" #bm "x" #bn "_w" #wm "x" #wn "_k" #bk "_s" #st,       \
             bk};
     SI_BF16_TILES(SI_SHAPE)
@@ -719,7 +803,7 @@ static hipError_t launch_sel(const BStepArgs &a, hipStream_t s) {
   } else if constexpr (JFMT == 1 && BK < 128) {
     return hipErrorInvalidValue;  // FP8 rows must be 128 bytes for the swizzle
   } else {
-    using C = Bf16DmaCfg<BM, BN, WM, WN, BK, JFMT, QP, ST, PP>;
+    using C = Bf16DmaCfg<BM, BN, WM, WN, BK, JFMT, QP, ST, PP ? 1 : 0, PP == 2 ? 4 : 0>;
     if constexpr (C::LDS_BYTES > 160 * 1024)
       return hipErrorInvalidValue;
     else
@@ -734,7 +818,8 @@ static constexpr bool sel_valid() {
   else if constexpr (JFMT == 1 && BK < 128)
     return false;
   else
-    return Bf16DmaCfg<BM, BN, WM, WN, BK, JFMT, QP, ST, PP>::LDS_BYTES <= 160 * 1024;
+    return Bf16DmaCfg<BM, BN, WM, WN, BK, JFMT, QP, ST, PP ? 1 : 0, PP == 2 ? 4 : 0>::LDS_BYTES <=
+           160 * 1024;
 }
 
 template <int JFMT, int QP>

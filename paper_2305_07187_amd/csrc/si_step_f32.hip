@@ -232,12 +232,10 @@ __global__ __launch_bounds__(C::NT) void step_batch_f32_kernel(StepArgs a,
 
 TileShape tile_shape(int32_t tile) {
   switch (tile) {
-#define SI_SHAPE(id, bm, bn, wm, wn, mb, bk, st, ks, pp) \
+#define SI_SHAPE(id, bm, bn, wm, wn, mb, bk, st, ks) \
   case id:                                           \
     return {bm, bn,                                  \
-            pp ? "step_f32_" #bm "x" #bn "_w" #wm "x" #wn "_mfma" #mb "_k" #bk "_s" #st "_a" #ks "_p1" \
-               : "step_f32_" #bm "x" #bn "_w" #wm "x" #wn "_mfma" #mb "_k" #bk "_s" #st "_a" #ks,    \
-            bk};
+            "step_f32_" #bm "x" #bn "_w" #wm "x" #wn "_mfma" #mb "_k" #bk "_s" #st "_a" #ks, bk};
     SI_F32_TILES(SI_SHAPE)
 #undef SI_SHAPE
     default: return {0, 0, "invalid", 0};
@@ -294,10 +292,10 @@ static hipError_t resident_launch(const StepArgs &a, const ResidentArgs &r, hipS
 hipError_t resident_f32_groups_per_cu(int32_t tile, int32_t order, int32_t wall, int *groups) {
   *groups = 0;
   switch (tile) {
-#define SI_RES_Q(id, bm, bn, wm, wn, mb, bk, st, ks, pp)                                  \
+#define SI_RES_Q(id, bm, bn, wm, wn, mb, bk, st, ks)                                  \
   case id:                                                                           \
     if constexpr (SI_HAS_RESIDENT(id))                                               \
-      return resident_groups<F32Cfg<bm, bn, wm, wn, mb, bk, st, ks, pp>>(order, wall, groups); \
+      return resident_groups<F32Cfg<bm, bn, wm, wn, mb, bk, st, ks>>(order, wall, groups); \
     else                                                                             \
       return hipSuccess;
     SI_F32_TILES(SI_RES_Q)
@@ -309,10 +307,10 @@ hipError_t resident_f32_groups_per_cu(int32_t tile, int32_t order, int32_t wall,
 hipError_t launch_resident_f32(int32_t tile, const StepArgs &a, const ResidentArgs &r,
                                hipStream_t s) {
   switch (tile) {
-#define SI_RES_L(id, bm, bn, wm, wn, mb, bk, st, ks, pp)                    \
+#define SI_RES_L(id, bm, bn, wm, wn, mb, bk, st, ks)                    \
   case id:                                                             \
     if constexpr (SI_HAS_RESIDENT(id))                                 \
-      return resident_launch<F32Cfg<bm, bn, wm, wn, mb, bk, st, ks, pp>>(a, r, s); \
+      return resident_launch<F32Cfg<bm, bn, wm, wn, mb, bk, st, ks>>(a, r, s); \
     else                                                               \
       return hipErrorInvalidValue;
     SI_F32_TILES(SI_RES_L)
@@ -343,9 +341,9 @@ hipError_t launch_step_batch_f32(const StepArgs &a, const BatchDesc *descs, cons
 hipError_t launch_step_f32(int32_t tile, const StepArgs &a, hipStream_t s) {
   if (a.ksplit > 1) return launch_step_f32_split(tile, a, s);
   switch (tile) {
-#define SI_LAUNCH(id, bm, bn, wm, wn, mb, bk, st, ks, pp) \
+#define SI_LAUNCH(id, bm, bn, wm, wn, mb, bk, st, ks) \
   case id:                                            \
-    return launch_cfg<F32Cfg<bm, bn, wm, wn, mb, bk, st, ks, pp>>(a, s);
+    return launch_cfg<F32Cfg<bm, bn, wm, wn, mb, bk, st, ks>>(a, s);
     SI_F32_TILES(SI_LAUNCH)
 #undef SI_LAUNCH
     default: return hipErrorInvalidValue;

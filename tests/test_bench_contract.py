@@ -21,15 +21,14 @@ def _tile_names():
     names = set()
     f32 = open(os.path.join(CSRC, "si_f32_gemm.h")).read()
     for m in re.finditer(r"X\((\d+),\s*(\d+),\s*(\d+),\s*(\d+),\s*(\d+),\s*(\d+),\s*(\d+),\s*(\d+),"
-                         r"\s*(\d+),\s*(\d+)\)", f32):
-        _, bm, bn, wm, wn, mb, bk, st, ks, pp = m.groups()
-        names.add(f"step_f32_{bm}x{bn}_w{wm}x{wn}_mfma{mb}_k{bk}_s{st}_a{ks}" +
-                  ("_p1" if pp == "1" else ""))
+                         r"\s*(\d+)\)", f32):
+        _, bm, bn, wm, wn, mb, bk, st, ks = m.groups()
+        names.add(f"step_f32_{bm}x{bn}_w{wm}x{wn}_mfma{mb}_k{bk}_s{st}_a{ks}")
     b16 = open(os.path.join(CSRC, "si_step_bf16.hip")).read()
     for m in re.finditer(r"X\((\d+),\s*(\d+),\s*(\d+),\s*(\d+),\s*(\d+),\s*(\d+),\s*(\d+),\s*(\d+)\)",
                          b16):
         _, bm, bn, wm, wn, bk, st, pp = m.groups()
-        names.add(f"step_bf16_{bm}x{bn}_w{wm}x{wn}_k{bk}_s{st}" + ("_p1" if pp == "1" else ""))
+        names.add(f"step_bf16_{bm}x{bn}_w{wm}x{wn}_k{bk}_s{st}" + ("" if pp == "0" else f"_p{pp}"))
     return names
 
 

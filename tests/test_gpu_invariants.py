@@ -77,8 +77,7 @@ def test_resume_is_bit_identical():
     assert torch.equal(xa, xb) and torch.equal(pa, pb)
 
 
-@pytest.mark.parametrize("group", [(1, 2, 4, 5, 7, 8, 9, 11, 13, 14, 15, 16, 17, 18, 25, 26, 27, 28, 29, 30, 32, 33, 34,
-                                    35, 36),
+@pytest.mark.parametrize("group", [(1, 2, 4, 5, 7, 8, 9, 11, 13, 14, 15, 16, 17, 18, 25, 26, 27, 28, 29, 30, 32, 33, 34),
                                    (3, 6, 10, 12)])
 def test_tiles_agree(group):
     # Tile shapes that use the same MFMA instruction add the contraction in

@@ -164,16 +164,17 @@ def test_fp8_and_bf16_j_identical():
 
 @pytest.mark.parametrize("precision,group", [
     ("bf16x_bf16j", (7, 8, 9, 10, 11, 12, 13, 15, 16, 17, 18, 20, 21, 22, 23, 24, 25, 26, 28, 29,
-                     31, 32, 33, 34)),
+                     30, 31, 32, 33)),
     ("bf16x_bf16j", (1, 2, 3, 4, 5, 6)),
-    ("bf16x_fp8j", (9, 13, 14, 19, 23, 25, 27, 30)),
-    ("bf16x_hiloj", (7, 8, 9, 10, 11, 12, 18, 20, 21, 22, 24, 26, 28, 29, 31, 33, 34)),
-    ("bf16x3_exactj", (7, 8, 11, 21, 22, 24, 26, 29, 31, 33, 34))])
+    ("bf16x_fp8j", (9, 13, 14, 19, 23, 25, 27, 32)),
+    ("bf16x_hiloj", (7, 8, 9, 10, 11, 12, 18, 20, 21, 22, 24, 26, 28, 30, 31, 33)),
+    ("bf16x3_exactj", (7, 8, 11, 21, 22, 24, 26, 30, 31, 33))])
 def test_bf16_tiles_agree(precision, group):
     # Within one pipeline kind every tile shape feeds the same contraction
     # indices to each MFMA and chains the MFMAs in the same order, so the
     # trajectories agree bit for bit whatever the block, wave or slab shape,
-    # and whether or not the ring is pipelined across slabs.
+    # whether or not the ring is pipelined across slabs, and whether the
+    # update runs in the matrix waves or in separate state waves.
     import torch
     announce(f"{precision} tiles agree {group}")
     n, r, S = 256, 256, 40
@@ -196,10 +197,10 @@ def test_bf16_tiles_agree(precision, group):
 
 
 @pytest.mark.parametrize("precision,group", [
-    ("bf16x_bf16j", (16, 18, 20, 21, 23, 28, 32, 33)),
-    ("bf16x_fp8j", (9, 19, 23, 27)),
-    ("bf16x_hiloj", (18, 20, 21, 28, 33)),
-    ("bf16x3_exactj", (11, 21, 22, 24, 26, 33, 34))])
+    ("bf16x_bf16j", (16, 18, 20, 21, 23, 28, 29, 30, 32)),
+    ("bf16x_fp8j", (9, 19, 23, 27, 32)),
+    ("bf16x_hiloj", (18, 20, 21, 28, 30)),
+    ("bf16x3_exactj", (11, 21, 22, 24, 26, 30, 31, 33))])
 def test_large_bf16_tiles_agree_ragged(precision, group):
     # The two-slab 128x256 / 256x128 rings against the three-slab rings on a
     # ragged shape: the row and replica padding differ between the tiles

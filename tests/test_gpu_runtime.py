@@ -170,8 +170,8 @@ def test_kernel_names_match_tile_tables_and_traffic_keys():
             name = m.info()["kernel_name"]
             assert m.info()["tile"] == tile
             m.close()
-            pat = r"step_f32_\d+x\d+_w\dx\d_mfma\d+_k\d+_s\d_a\d(_p1)?" if prec == "fp32" else \
-                r"step_bf16_\d+x\d+_w\dx\d_k\d+_s\d(_p1)?"
+            pat = r"step_f32_\d+x\d+_w\dx\d_mfma\d+_k\d+_s\d_a\d" if prec == "fp32" else \
+                r"step_bf16_\d+x\d+_w\dx\d_k\d+_s\d(_p[12])?"
             assert re.fullmatch(pat, name), (prec, tile, name)
             names.add(name)
         assert names, prec
