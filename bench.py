@@ -51,6 +51,7 @@ CHECK_EVERY = 50
 PEAK_FP32_MFMA_TFLOPS = 157.3
 PEAK_BF16_MFMA_TFLOPS = 2500.0
 PEAK_HBM_GBS = 8000.0
+PEAK_INT8_MFMA_TOPS = 5000.0
 FORMS = ["bf16x_fp8j", "bf16x_bf16j", "bf16x3_exactj"]
 # HBM/MALL bytes per launch of a step kernel, from two rocprofv3 counter
 # passes (FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000; the factors come from an
@@ -488,6 +489,26 @@ def time_to_target(si, J, n, r, iters, every, stream, runs_per_form):
             "forms": forms}
 
 
+def energy_readout(si, model, n, r, calls, stream):
+    """HIP-event time of the exact Eq. (1) readout of all replicas (sign of q,
+    int8 product G = J.S on the matrix cores, per-replica reduction and
+    finalisation), per call; 2 N^2 R int8 operations of algorithmic work."""
+    import torch
+    e = torch.empty(r, dtype=torch.int32, device="cuda:0")
+    for _ in range(5):
+        si.spring_ising_energy(model.ctx, e, None)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(calls):
+        si.spring_ising_energy(model.ctx, e, None)
+    b.record(stream)
+    torch.cuda.synchronize()
+    us = 1000.0 * a.elapsed_time(b) / calls
+    tops = 2.0 * n * n * r / (us * 1e-6) / 1e12
+    return {"us_per_call": us, "calls": calls, "int8_tops_incl_sign_and_finalize": tops,
+            "frac_of_int8_peak": tops / PEAK_INT8_MFMA_TOPS}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -508,6 +529,7 @@ def main():
     ap.add_argument("--tile", type=int, default=0, help="step-kernel tile id (0 = automatic)")
     ap.add_argument("--precision", default="fp32", help="fp32 | bf16x_fp8j | bf16x_bf16j | "
                     "bf16x_hiloj | bf16x3_exactj (the headline line is fp32)")
+    ap.add_argument("--energy-calls", type=int, default=200, help=argparse.SUPPRESS)
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="first run one elementwise kernel reading and writing this many MiB "
                          "(calibration of the HBM byte counters)")
@@ -581,6 +603,9 @@ def main():
         "result": {"best_cut": float(cuts.max()), "mean_cut": float(cuts.mean()),
                    "best_energy": float(e.min()), "mean_energy": float(e.mean())},
     }
+
+    if bool(info["j_integer"]) and args.energy_calls > 0:
+        out["energy_readout"] = energy_readout(si, model, n, r, args.energy_calls, stream)
 
     if fp32_line and not args.no_forms:
         # the same workload with the positions' wall at |q| = 1 instead of sqrt 2

@@ -2,12 +2,13 @@
 //
 // For integer couplings |J_ij| <= 127 the energy of s = sign(q) is exact:
 // G = J.S is an int8 x int8 product with int32 accumulation
-// (v_mfma_i32_16x16x32_i8), and sum_i s_i (G_i + 2 h_i) = 2 sum_{i<j} J_ij
+// (v_mfma_i32_32x32x32_i8 for a single instance, v_mfma_i32_16x16x32_i8 for
+// the batch's 64 x 64 items), and sum_i s_i (G_i + 2 h_i) = 2 sum_{i<j} J_ij
 // s_i s_j + 2 sum_i h_i s_i is even, so E = -(that sum)/2 is exact.
 // Partial sums from all workgroups are combined with integer atomics, whose
 // result does not depend on their order.
 //
-// MFMA operand layout (one 16x16 block, K = 32): lane l supplies the 8 bytes
+// Batch item layout (one 16x16 block, K = 32): lane l supplies the 8 bytes
 // A[l%16][8(l/16) .. 8(l/16)+7] and B[8(l/16) .. +7][l%16]; D as for the FP32
 // shape.  Each lane reads 16 contiguous bytes per operand and per 64-byte
 // slab; MFMA s = 0, 1 uses bytes 8s .. 8s+7 of them (a permutation of the
@@ -102,11 +103,120 @@ __device__ __forceinline__ void energy_i8_tile(const int8_t *__restrict__ J8,
   }
 }
 
-__global__ __launch_bounds__(256) void energy_i8_kernel(const int8_t *__restrict__ J8,
+// ---------------------------------------------------------------------------
+// Single-instance energy on gfx950's int8 shape v_mfma_i32_32x32x32_i8.
+// Lane l supplies the 16 bytes A[l%32][16(l/32) .. +15] and
+// B[16(l/32) .. +15][l%32] of each 32-deep contraction step (A and B use the
+// same assignment of contraction bytes to lanes, so the product is a plain
+// sum over them); the result D[8(v/4) + 4(l/32) + v%4][l%32] lands in
+// accumulator v < 16.  One 128 x 64 output tile per workgroup, eight waves of
+// 32 x 32, the J and S slabs (QBK contraction bytes deep) copied straight
+// into a three-slot LDS ring with the chunk swizzle of their rows.
+// ---------------------------------------------------------------------------
+namespace {
+constexpr int QBM = 128, QBN = 64, QBK = 128, QST = 3, QNT = 512, QNW = QNT / 64;
+constexpr int QSLOT = (QBM + QBN) * QBK;  // bytes per ring slot
+constexpr int QCH = QBK / 16;             // 16-byte chunks per slab row
+constexpr int QRPD = 64 / QCH;            // rows written by one wave-wide load
+constexpr int QAD = QBM / QRPD / QNW, QBD = QBN / QRPD / QNW;  // loads per wave per slab
+constexpr int QL = QAD + QBD;
+static_assert(QAD >= 1 && QBD >= 1 && (QST - 2) * QL <= 63, "energy ring");
+}  // namespace
+
+typedef int intx16 __attribute__((ext_vector_type(16)));
+typedef __attribute__((address_space(3))) void lds_void_e;
+typedef __attribute__((address_space(1))) const void gbl_void_e;
+
+template <int N>
+__device__ __forceinline__ void e_wait_barrier() {
+  asm volatile("s_waitcnt vmcnt(%0)\n\ts_barrier" ::"n"(N) : "memory");
+}
+
+__global__ __launch_bounds__(QNT) void energy_i8_kernel(const int8_t *__restrict__ J8,
                                                         const int8_t *__restrict__ S8,
                                                         const int8_t *__restrict__ h8,
-                                                        int32_t *__restrict__ acc_out, int ld) {
-  energy_i8_tile(J8, S8, h8, acc_out, ld, blockIdx.x * EBM, blockIdx.y * EBN);
+                                                        int32_t *__restrict__ acc_out, int ld,
+                                                        int r_pad) {
+  __shared__ __attribute__((aligned(16))) int8_t smem[QST * QSLOT];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wy = wave >> 1, wx = wave & 1;  // 4 x 2 waves of 32 x 32
+  const int ncol = r_pad / QBN;
+  const int t = xcd_tile(blockIdx.x, gridDim.x);
+  const int m0 = (t / ncol) * QBM, n0 = (t % ncol) * QBN;
+  // A wave-wide direct-to-LDS load writes 64 x 16 bytes: QRPD rows.  Lane
+  // L fills position L % QCH of row L / QCH with the chunk that belongs
+  // there (chunk c of row r is stored at position c ^ swz(r)).
+  const int drow = lane / QCH, dch = lane % QCH;
+  const int8_t *srcA[QAD];
+  const int8_t *srcB[QBD];
+#pragma unroll
+  for (int d = 0; d < QAD; ++d) {
+    const int row = (wave * QAD + d) * QRPD + drow;
+    srcA[d] = J8 + (size_t)(m0 + row) * ld + ((dch ^ lds_swz<QCH>(row)) << 4);
+  }
+#pragma unroll
+  for (int d = 0; d < QBD; ++d) {
+    const int row = (wave * QBD + d) * QRPD + drow;
+    srcB[d] = S8 + (size_t)(n0 + row) * ld + ((dch ^ lds_swz<QCH>(row)) << 4);
+  }
+  auto issue = [&](int kt, int slot) {
+    int8_t *st = smem + slot * QSLOT;
+#pragma unroll
+    for (int d = 0; d < QAD; ++d)
+      __builtin_amdgcn_global_load_lds((gbl_void_e *)(srcA[d] + (size_t)kt * QBK),
+                                       (lds_void_e *)(st + (wave * QAD + d) * QRPD * QBK), 16, 0,
+                                       0);
+#pragma unroll
+    for (int d = 0; d < QBD; ++d)
+      __builtin_amdgcn_global_load_lds((gbl_void_e *)(srcB[d] + (size_t)kt * QBK),
+                                       (lds_void_e *)(st + (QBM + (wave * QBD + d) * QRPD) * QBK),
+                                       16, 0, 0);
+  };
+  const int nk = ld / QBK;
+#pragma unroll
+  for (int s = 0; s < QST - 1; ++s)
+    if (s < nk) issue(s, s);
+  intx16 acc;
+#pragma unroll
+  for (int v = 0; v < 16; ++v) acc[v] = 0;
+  const int ra = wy * 32 + (lane & 31), rb = wx * 32 + (lane & 31), h = lane >> 5;
+  int rd = 0, wr = QST - 1;
+  for (int kt = 0; kt < nk; ++kt) {
+    if (kt + QST - 1 < nk) {
+      e_wait_barrier<(QST - 2) * QL>();
+      issue(kt + QST - 1, wr);
+    } else {
+      e_wait_barrier<0>();
+    }
+    wr = wr + 1 == QST ? 0 : wr + 1;
+    const int8_t *st = smem + rd * QSLOT;
+    rd = rd + 1 == QST ? 0 : rd + 1;
+#pragma unroll
+    for (int kk = 0; kk < QBK / 32; ++kk) {
+      const int ch = kk * 2 + h;  // 16-byte chunk of this lane in the slab row
+      const intx4 a =
+          *reinterpret_cast<const intx4 *>(st + ra * QBK + ((ch ^ lds_swz<QCH>(ra)) << 4));
+      const intx4 b = *reinterpret_cast<const intx4 *>(st + (QBM + rb) * QBK +
+                                                       ((ch ^ lds_swz<QCH>(rb)) << 4));
+      acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(a, b, acc, 0, 0, 0);
+    }
+  }
+  // sum_i s_i (G_i + 2 h_i) over this wave's 32 rows for each of its columns
+  const int col = n0 + wx * 32 + (lane & 31);
+  int c = 0;
+#pragma unroll
+  for (int g = 0; g < 4; ++g) {
+    const int row = m0 + wy * 32 + g * 8 + h * 4;
+    const char4 s4 = *reinterpret_cast<const char4 *>(S8 + (size_t)col * ld + row);
+    char4 h4 = make_char4(0, 0, 0, 0);
+    if (h8) h4 = *reinterpret_cast<const char4 *>(h8 + row);
+    c += (int)s4.x * (acc[4 * g] + 2 * (int)h4.x);
+    c += (int)s4.y * (acc[4 * g + 1] + 2 * (int)h4.y);
+    c += (int)s4.z * (acc[4 * g + 2] + 2 * (int)h4.z);
+    c += (int)s4.w * (acc[4 * g + 3] + 2 * (int)h4.w);
+  }
+  c += __shfl_xor(c, 32);
+  if (h == 0) atomicAdd(acc_out + col, c);
 }
 
 // Batch: work item (instance, row tile, column tile) over the instances with
@@ -173,9 +283,8 @@ hipError_t launch_sign(const float *q, int8_t *s8, int32_t n_pad, int32_t r_pad,
 
 hipError_t launch_energy_i8(const int8_t *J8, const int8_t *S8, const int8_t *h8, int32_t *acc,
                             int32_t n_pad, int32_t r_pad, hipStream_t s) {
-  if (n_pad % EBM || r_pad % EBN) return hipErrorInvalidValue;
-  dim3 grid(n_pad / EBM, r_pad / EBN);
-  energy_i8_kernel<<<grid, 256, 0, s>>>(J8, S8, h8, acc, n_pad);
+  if (n_pad % QBM || n_pad % QBK || r_pad % QBN) return hipErrorInvalidValue;
+  energy_i8_kernel<<<(n_pad / QBM) * (r_pad / QBN), QNT, 0, s>>>(J8, S8, h8, acc, n_pad, r_pad);
   return hipGetLastError();
 }
 
