@@ -51,6 +51,15 @@ def test_adjoint_vs_oracle_small():
              f"zeta {_rel(gz, gzo):.2e}")
     assert abs(L - Lo) <= 1e-5 * abs(Lo)
     assert _rel(gd, gdo) <= 1e-4 and _rel(gz, gzo) <= 1e-4
+    # element by element: every entry at least 1e-3 of the largest within 1e-4
+    # of its own value (entries far below the largest are otherwise unchecked)
+    for name, g, go in (("dt", gd, gdo), ("zeta", gz, gzo)):
+        big = np.abs(go) >= 1e-3 * np.abs(go).max()
+        rel = np.abs(g[big] - go[big]) / np.abs(go[big])
+        announce(f"  {name}: {int(big.sum())} of {len(go)} entries checked, worst element-wise "
+                 f"rel err {rel.max():.2e}")
+        assert big.sum() >= len(go) // 2
+        assert rel.max() <= 1e-4, (name, int(np.argmax(rel)))
 
 
 @pytest.mark.parametrize("which", ["dt", "zeta"])

@@ -67,6 +67,30 @@ def test_batch_vs_oracle():
         assert eq <= 1e-5 and ep <= 1e-5
 
 
+def test_batch_vs_oracle_large_instances():
+    # A +-1 and a Gaussian instance of at least 2048 spins inside one batch
+    # with smaller ones, in the FP32 batch, against the oracle on sampled
+    # replicas for the first 10 steps (the window in which FP32 arithmetic
+    # stays within 1e-5 of FP64 at this size).
+    import torch
+    specs = [(2048, "pm1"), (2100, "gauss"), (300, "pm1"), (777, "gauss")]
+    announce(f"batch with N >= 2048 instances vs oracle, 10 steps {specs}")
+    S, r, steps = 1000, 64, 10
+    b, Js, xs = _batch(specs, S, r=r)
+    b.run(steps)
+    xb, pb, _ = b.state()
+    torch.cuda.synchronize()
+    dt, zeta = oracle_schedules(S)
+    cols = [0, 1, 31, 32, 62, 63]
+    for i, (n, kind) in enumerate(specs):
+        ref = oracle.run(Js[i].astype(np.float64), xs[i][cols].T.astype(np.float64), None, dt,
+                         zeta, qmax=QMAX, n_steps=steps)
+        eq = rel_err(xb[i].cpu().numpy()[cols], ref["Q"])
+        ep = rel_err(pb[i].cpu().numpy()[cols], ref["P"])
+        announce(f"  instance {i} N={n} {kind}: rel err q {eq:.2e} p {ep:.2e}")
+        assert eq <= 1e-5 and ep <= 1e-5
+
+
 def test_batch_energies_and_layout():
     import torch
     si = ensure_built()
