@@ -351,6 +351,23 @@ si_status spring_ising_set_state(si_ctx *ctx, const float *x, const float *p, in
 si_status spring_ising_relaxed_energy_grad(si_ctx *ctx, int32_t ckpt_every, double *loss,
                                            double *dL_ddt, double *dL_dzeta);
 
+/* The same gradient in two halves, for callers that evaluate the loss first
+ * and ask for its gradient later (an autograd function's forward and
+ * backward).  relaxed_energy_forward runs the remaining steps with
+ * checkpoints every ckpt_every steps, writes loss (device, 1 double) and
+ * records a tape in the context: the checkpoints, the seed of the reverse
+ * sweep, the start step t0 and the context's state epoch.  Every call that
+ * changes the trajectory (set_schedule, set_field, set_state, step, run,
+ * set_ksplit, autotune) advances the epoch.
+ * relaxed_energy_backward runs the reverse sweep over that tape and writes
+ * dL_ddt, dL_dzeta (device, total_steps doubles each, entries n < t0 set to
+ * 0).  It consumes the tape: without a forward half since the last change of
+ * the trajectory, or a second time after one, it returns SI_ERR_STATE and
+ * writes nothing.  Conditions and workspace as for relaxed_energy_grad,
+ * whose results equal forward followed by backward bit for bit. */
+si_status spring_ising_relaxed_energy_forward(si_ctx *ctx, int32_t ckpt_every, double *loss);
+si_status spring_ising_relaxed_energy_backward(si_ctx *ctx, double *dL_ddt, double *dL_dzeta);
+
 /* Fill *info (host). */
 si_status spring_ising_info(si_ctx *ctx, si_info *info);
 

@@ -159,6 +159,14 @@ struct si_ctx {
   int32_t e_every = 0, e_rows = 0;
   double *etrace = nullptr;
   int64_t out_rows() const { return n_inst ? (int64_t)n_inst * r : (int64_t)r; }
+  // every call that changes the trajectory (schedule, field, state, steps,
+  // kernel choice) bumps the epoch; the adjoint's forward half records it
+  int64_t epoch = 0;
+  struct {
+    bool valid = false;
+    int64_t epoch = 0;
+    int32_t t0 = 0, ckpt = 0;
+  } tape;
   // adjoint workspace
   float *adj_ckpt = nullptr, *adj_seg = nullptr, *adj_lam = nullptr;
   uint8_t *adj_mask = nullptr;
@@ -791,6 +799,7 @@ si_status spring_ising_set_schedule(si_ctx *c, const float *dt, const float *zet
   SI_USABLE(c);
   if (!is_device_ptr(dt) || !is_device_ptr(zeta))
     return fail(SI_ERR_INVALID, "set_schedule: dt and zeta must be device pointers");
+  c->epoch++;
   const size_t bytes = sizeof(float) * c->prm.total_steps;
   SI_HIP(c, hipMemcpyAsync(c->dt, dt, bytes, hipMemcpyDeviceToDevice, c->stream));
   SI_HIP(c, hipMemcpyAsync(c->zeta, zeta, bytes, hipMemcpyDeviceToDevice, c->stream));
@@ -809,6 +818,7 @@ si_status spring_ising_get_schedule(si_ctx *c, float *dt, float *zeta) {
 
 si_status spring_ising_set_field(si_ctx *c, const float *h) {
   SI_USABLE(c);
+  c->epoch++;
   // captured launch sequences hold the field pointer (or its absence) in
   // their kernel arguments, so none of them may be replayed after a change
   c->drop_graphs();
@@ -974,17 +984,17 @@ static si_status do_steps(si_ctx *c, int32_t n_steps) {
   return SI_OK;
 }
 
-si_status spring_ising_relaxed_energy_grad(si_ctx *c, int32_t ckpt_every, double *loss,
-                                           double *g_dt, double *g_zeta) {
-  SI_USABLE(c);
-  if (ckpt_every < 1) return fail(SI_ERR_INVALID, "relaxed_energy_grad: ckpt_every < 1");
-  if (!is_device_ptr(loss) || !is_device_ptr(g_dt) || !is_device_ptr(g_zeta))
-    return fail(SI_ERR_INVALID, "relaxed_energy_grad: outputs must be device pointers");
+// Adjoint, forward half: run from the current step t0 to the end of the
+// schedule, keeping the state at the start of every segment of ckpt_every
+// steps, then the seed lq_S = -(1/R) J q_S, lp_S = 0 and the loss.  Records
+// the tape that the backward half reads.
+static si_status adj_forward(si_ctx *c, int32_t C, double *loss) {
   if (c->prm.order != SI_ORDER_PAPER || c->prm.wall != SI_WALL_CLAMP ||
       c->prm.precision != SI_PREC_FP32 || c->has_field || c->n_inst)
-    return fail(SI_ERR_UNSUPPORTED, "relaxed_energy_grad: needs paper order, clamping walls, "
+    return fail(SI_ERR_UNSUPPORTED, "relaxed energy adjoint: needs paper order, clamping walls, "
                 "FP32 precision and no field");
-  const int32_t S = c->prm.total_steps, t0 = c->t, C = ckpt_every;
+  c->tape.valid = false;
+  const int32_t S = c->prm.total_steps, t0 = c->t;
   const int32_t nseg = (S - t0 + C - 1) / C;
   const int64_t NR = (int64_t)c->n_pad * c->r_pad;
   const int32_t asplit = adj_split(c);
@@ -1009,9 +1019,6 @@ si_status spring_ising_relaxed_energy_grad(si_ctx *c, int32_t ckpt_every, double
     c->adj_part_cap = part_need;
   }
   const float inv_r = 1.0f / (float)c->r, inv_m = 1.0f / c->prm.m, k = c->prm.k;
-  SI_HIP(c, launch_fill_f64(g_dt, S, 0.0, c->stream));
-  SI_HIP(c, launch_fill_f64(g_zeta, S, 0.0, c->stream));
-
   // forward with checkpoints at the start of every segment
   for (int32_t sg = 0; sg < nseg; ++sg) {
     float *ck = c->adj_ckpt + (int64_t)sg * 2 * NR;
@@ -1024,13 +1031,37 @@ si_status spring_ising_relaxed_energy_grad(si_ctx *c, int32_t ckpt_every, double
     if (st != SI_OK) return st;
   }
   // seed: lq_S = -(1/R) J q_S, lp_S = 0, and the loss
-  float *lam[2][2] = {{c->adj_lam, c->adj_lam + NR}, {c->adj_lam + 2 * NR, c->adj_lam + 3 * NR}};
-  int lc = 0;
-  SI_HIP(c, launch_adj_seed(c->J, c->q[c->cur], lam[0][0], lam[0][1], c->adj_part, c->n_pad,
-                            c->r_pad, inv_r, c->stream));
+  SI_HIP(c, launch_adj_seed(c->J, c->q[c->cur], c->adj_lam, c->adj_lam + NR, c->adj_part,
+                            c->n_pad, c->r_pad, inv_r, c->stream));
   SI_HIP(c, launch_adj_reduce(c->adj_part, nwg_seed, 0, loss, nullptr, nullptr, c->dt, c->zeta, 0,
                               1, k, inv_m, c->r, c->stream));
-  // reverse sweep, one segment at a time
+  c->tape.valid = true;
+  c->tape.epoch = c->epoch;
+  c->tape.t0 = t0;
+  c->tape.ckpt = C;
+  return SI_OK;
+}
+
+// Adjoint, backward half: the reverse sweep over the recorded tape, one
+// segment at a time (forward recomputed from its checkpoint, recording the
+// wall masks), and the gradient entries of every step in one launch.
+static si_status adj_backward(si_ctx *c, double *g_dt, double *g_zeta) {
+  if (!c->tape.valid || c->tape.epoch != c->epoch)
+    return fail(SI_ERR_STATE, "relaxed energy backward: no forward half since the last change of "
+                "the trajectory (schedule, field, state, steps or kernel)");
+  const int32_t S = c->prm.total_steps, t0 = c->tape.t0, C = c->tape.ckpt;
+  const int32_t nseg = (S - t0 + C - 1) / C;
+  const int64_t NR = (int64_t)c->n_pad * c->r_pad;
+  const int32_t asplit = adj_split(c);
+  const int32_t nwg = asplit > 1 ? adj_split_groups(c->n_pad, c->r_pad)
+                                 : (c->n_pad / ADJ_BM) * (c->r_pad / ADJ_BN);
+  const float inv_m = 1.0f / c->prm.m, k = c->prm.k;
+  SI_HIP(c, launch_fill_f64(g_dt, S, 0.0, c->stream));
+  SI_HIP(c, launch_fill_f64(g_zeta, S, 0.0, c->stream));
+  float *lam[2][2] = {{c->adj_lam, c->adj_lam + NR}, {c->adj_lam + 2 * NR, c->adj_lam + 3 * NR}};
+  int lc = 0;
+  // the multipliers are rewritten by the sweep: one backward per forward
+  c->tape.valid = false;
   StepArgs a = step_args(c);
   for (int32_t sg = nseg - 1; sg >= 0; --sg) {
     const int32_t t_a = t0 + sg * C;
@@ -1071,10 +1102,37 @@ si_status spring_ising_relaxed_energy_grad(si_ctx *c, int32_t ckpt_every, double
   return SI_OK;
 }
 
+si_status spring_ising_relaxed_energy_forward(si_ctx *c, int32_t ckpt_every, double *loss) {
+  SI_USABLE(c);
+  if (ckpt_every < 1) return fail(SI_ERR_INVALID, "relaxed_energy_forward: ckpt_every < 1");
+  if (!is_device_ptr(loss))
+    return fail(SI_ERR_INVALID, "relaxed_energy_forward: loss must be a device pointer");
+  return adj_forward(c, ckpt_every, loss);
+}
+
+si_status spring_ising_relaxed_energy_backward(si_ctx *c, double *g_dt, double *g_zeta) {
+  SI_USABLE(c);
+  if (!is_device_ptr(g_dt) || !is_device_ptr(g_zeta))
+    return fail(SI_ERR_INVALID, "relaxed_energy_backward: outputs must be device pointers");
+  return adj_backward(c, g_dt, g_zeta);
+}
+
+si_status spring_ising_relaxed_energy_grad(si_ctx *c, int32_t ckpt_every, double *loss,
+                                           double *g_dt, double *g_zeta) {
+  SI_USABLE(c);
+  if (ckpt_every < 1) return fail(SI_ERR_INVALID, "relaxed_energy_grad: ckpt_every < 1");
+  if (!is_device_ptr(loss) || !is_device_ptr(g_dt) || !is_device_ptr(g_zeta))
+    return fail(SI_ERR_INVALID, "relaxed_energy_grad: outputs must be device pointers");
+  si_status st = adj_forward(c, ckpt_every, loss);
+  if (st != SI_OK) return st;
+  return adj_backward(c, g_dt, g_zeta);
+}
+
 si_status spring_ising_step(si_ctx *c) {
   SI_USABLE(c);
   if (c->t >= c->prm.total_steps)
     return fail(SI_ERR_RANGE, "step: t=%d reached total_steps=%d", c->t, c->prm.total_steps);
+  c->epoch++;
   return do_steps(c, 1);
 }
 
@@ -1170,6 +1228,7 @@ si_status spring_ising_run(si_ctx *c, int32_t n_steps) {
   if ((int64_t)c->t + n_steps > c->prm.total_steps)
     return fail(SI_ERR_RANGE, "run: t=%d + n_steps=%d exceeds total_steps=%d", c->t, n_steps,
                 c->prm.total_steps);
+  c->epoch++;
   if (c->resident_min_steps > 0 && n_steps >= c->resident_min_steps && n_steps > 1 &&
       c->e_every == 0) {
     const int32_t groups = resident_groups(c);
@@ -1185,6 +1244,7 @@ si_status spring_ising_set_ksplit(si_ctx *c, int32_t ksplit) {
   if (ksplit >= 2 && (c->n_inst || c->qplanes || !tile_has_split(c->tile)))
     return fail(SI_ERR_UNSUPPORTED, "set_ksplit: the split contraction needs a single FP32 "
                 "instance on a tile with a split form (tile %d)", c->tile);
+  c->epoch++;
   c->ksplit_mode = ksplit;
   SI_HIP(c, ensure_split_ws(c));
   c->drop_graphs();
@@ -1228,6 +1288,7 @@ si_status spring_ising_autotune(si_ctx *c, int32_t steps, int32_t *best_tile, fl
   if (c->n_inst) return fail(SI_ERR_UNSUPPORTED, "autotune: not available for a batch");
   if ((int64_t)c->t + steps > c->prm.total_steps)
     return fail(SI_ERR_RANGE, "autotune: %d steps from t=%d exceed total_steps", steps, c->t);
+  c->epoch++;
   const int64_t NR = (int64_t)c->n_pad * c->r_pad;
   // saved state: q and p in the adjoint's segment buffer, the BF16 planes of
   // q in a buffer of their own; both kept for later calls
@@ -1505,6 +1566,7 @@ si_status spring_ising_set_state(si_ctx *c, const float *x, const float *p, int3
     return fail(SI_ERR_INVALID, "set_state: x and p must be device pointers");
   if (t < 0 || t > c->prm.total_steps)
     return fail(SI_ERR_RANGE, "set_state: t=%d outside [0, %d]", t, c->prm.total_steps);
+  c->epoch++;
   if (c->best_valid)
     SI_HIP(c, launch_zero_i32(c->best_valid, c->n_inst ? c->out_rows() : c->r_pad, c->stream));
   c->best_any = false;

@@ -90,6 +90,8 @@ _SIGNATURES = {
     "spring_ising_set_state": [_P, _P, _P, _I],
     "spring_ising_info": [_P, ctypes.POINTER(si_info)],
     "spring_ising_relaxed_energy_grad": [_P, _I, _P, _P, _P],
+    "spring_ising_relaxed_energy_forward": [_P, _I, _P],
+    "spring_ising_relaxed_energy_backward": [_P, _P, _P],
     "spring_ising_set_graph": [_P, _I],
     "spring_ising_set_resident": [_P, _I],
     "spring_ising_set_ksplit": [_P, _I],
@@ -304,6 +306,19 @@ def spring_ising_relaxed_energy_grad(ctx, ckpt_every, loss, dl_ddt, dl_dzeta):
     _check(load_library().spring_ising_relaxed_energy_grad(
         ctx, int(ckpt_every), _ptr(loss, torch.float64, 1, "loss"),
         _ptr(dl_ddt, torch.float64, name="dL_ddt"), _ptr(dl_dzeta, torch.float64, name="dL_dzeta")))
+
+
+def spring_ising_relaxed_energy_forward(ctx, ckpt_every, loss):
+    import torch
+    _check(load_library().spring_ising_relaxed_energy_forward(
+        ctx, int(ckpt_every), _ptr(loss, torch.float64, 1, "loss")))
+
+
+def spring_ising_relaxed_energy_backward(ctx, dl_ddt, dl_dzeta):
+    import torch
+    _check(load_library().spring_ising_relaxed_energy_backward(
+        ctx, _ptr(dl_ddt, torch.float64, name="dL_ddt"),
+        _ptr(dl_dzeta, torch.float64, name="dL_dzeta")))
 
 
 def spring_ising_update_best(ctx):
@@ -590,3 +605,23 @@ class SpringIsing:
         g_z = torch.empty_like(g_dt)
         spring_ising_relaxed_energy_grad(self.ctx, ckpt_every, loss, g_dt, g_z)
         return loss, g_dt, g_z
+
+    def relaxed_energy_forward(self, ckpt_every=100):
+        """Forward half of relaxed_energy_grad: run the remaining steps with
+        checkpoints and return the loss (float64 CUDA tensor [1]); the tape
+        stays in the context for relaxed_energy_backward."""
+        import torch
+        loss = torch.empty(1, dtype=torch.float64, device=self.device)
+        spring_ising_relaxed_energy_forward(self.ctx, ckpt_every, loss)
+        return loss
+
+    def relaxed_energy_backward(self):
+        """Reverse sweep over the tape of the last relaxed_energy_forward:
+        (dL/ddt, dL/dzeta) as float64 CUDA tensors.  Raises SpringIsingError
+        (SI_ERR_STATE) when the trajectory changed since that forward half, or
+        when its tape was already used."""
+        import torch
+        g_dt = torch.empty(self.total_steps, dtype=torch.float64, device=self.device)
+        g_z = torch.empty_like(g_dt)
+        spring_ising_relaxed_energy_backward(self.ctx, g_dt, g_z)
+        return g_dt, g_z

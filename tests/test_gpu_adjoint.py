@@ -243,3 +243,110 @@ def test_adjoint_unsupported_configurations():
             m.relaxed_energy_grad(5)
         assert e.value.status == si.SI_ERR_UNSUPPORTED
         m.close()
+
+
+def test_forward_backward_halves_equal_combined():
+    import torch
+    si = ensure_built()
+    announce("relaxed energy forward/backward halves vs combined call")
+    n, r, S = 200, 16, 90
+    J = instances.make_pm1(n, 2)
+    x0 = instances.make_x0(n, r, 2)
+    dt, zeta = _sched(1000, S)
+    L, gd, gz = _grad(J, x0, dt, zeta, ckpt=25)
+    m = si.SpringIsing(to_dev(J), to_dev(x0), total_steps=S)
+    m.set_schedule(to_dev(np.asarray(dt, np.float32)), to_dev(np.asarray(zeta, np.float32)))
+    loss = m.relaxed_energy_forward(25)
+    torch.cuda.synchronize()
+    assert m.info()["t"] == S
+    # state reads do not touch the tape
+    m.state()
+    m.energy()
+    m.spins()
+    g_dt, g_z = m.relaxed_energy_backward()
+    torch.cuda.synchronize()
+    assert float(loss.cpu()[0]) == L
+    assert np.array_equal(g_dt.cpu().numpy(), gd) and np.array_equal(g_z.cpu().numpy(), gz)
+    # the tape is consumed by the sweep
+    with pytest.raises(si.SpringIsingError) as e:
+        m.relaxed_energy_backward()
+    assert e.value.status == si.SI_ERR_STATE
+    m.close()
+
+
+def test_backward_rejects_a_changed_trajectory():
+    import torch
+    si = ensure_built()
+    announce("relaxed energy backward after a change of the trajectory")
+    n, r, S = 64, 4, 30
+    J = to_dev(instances.make_pm1(n, 3))
+    x0 = to_dev(instances.make_x0(n, r, 3))
+    dt, zeta = _sched(1000, S)
+    dt_d, z_d = to_dev(np.asarray(dt, np.float32)), to_dev(np.asarray(zeta, np.float32))
+    # every change starts from a fresh forward half over steps 10..S
+    changes = {
+        "set_schedule": lambda m: m.set_schedule(dt_d, z_d),
+        "set_state": lambda m: m.set_state(x0, None, 10),
+        "step": lambda m: (m.set_state(x0, None, 10), m.relaxed_energy_forward(10),
+                           m.set_state(x0, None, S - 1), m.step()),
+        "run": lambda m: (m.set_state(x0, None, 10), m.relaxed_energy_forward(10),
+                          m.set_state(x0, None, S - 3), m.run(3)),
+        "set_ksplit": lambda m: m.set_ksplit(1),
+    }
+    for name, change in changes.items():
+        m = si.SpringIsing(J, x0, total_steps=S)
+        m.set_schedule(dt_d, z_d)
+        m.set_state(x0, None, 10)
+        m.relaxed_energy_forward(10)
+        change(m)
+        torch.cuda.synchronize()
+        with pytest.raises(si.SpringIsingError) as e:
+            m.relaxed_energy_backward()
+        assert e.value.status == si.SI_ERR_STATE, name
+        # a fresh forward half makes backward available again
+        m.set_state(x0, None, 10)
+        m.relaxed_energy_forward(10)
+        g_dt, g_z = m.relaxed_energy_backward()
+        torch.cuda.synchronize()
+        g = g_dt.cpu().numpy()
+        assert np.all(np.isfinite(g)) and np.all(g[:10] == 0.0), name
+        m.close()
+    # a call that fails its argument checks leaves the tape alone
+    m = si.SpringIsing(J, x0, total_steps=S)
+    m.set_schedule(dt_d, z_d)
+    m.relaxed_energy_forward(10)
+    with pytest.raises(si.SpringIsingError):
+        m.step()  # t == total_steps
+    g_dt, _ = m.relaxed_energy_backward()
+    torch.cuda.synchronize()
+    assert np.all(np.isfinite(g_dt.cpu().numpy()))
+    m.close()
+    # backward before any forward half
+    m = si.SpringIsing(J, x0, total_steps=S)
+    with pytest.raises(si.SpringIsingError) as e:
+        m.relaxed_energy_backward()
+    assert e.value.status == si.SI_ERR_STATE
+    m.close()
+
+
+def test_autograd_defers_the_sweep():
+    import torch
+    from paper_2305_07187_amd.autograd import SpringIsingRelaxedEnergy
+    announce("autograd Function keeps the tape until backward")
+    n, r, S = 100, 8, 40
+    J = instances.make_pm1(n, 4)
+    x0 = instances.make_x0(n, r, 4)
+    dt_np, z_np = _sched(1000, S)
+    dt = to_dev(dt_np).requires_grad_(True)
+    z = to_dev(z_np)
+    loss = SpringIsingRelaxedEnergy.apply(to_dev(J), to_dev(x0), None, dt, z, 10)
+    node = loss.grad_fn
+    assert node.model is not None and node.model.ctx is not None
+    loss.backward()
+    assert node.model is None
+    L, gd, gz = _grad(J, x0, dt_np, z_np, ckpt=10)
+    assert float(loss) == L
+    np.testing.assert_allclose(dt.grad.cpu().numpy(), gd.astype(np.float32), rtol=1e-6)
+    # no schedule requires a gradient: the context is released in forward
+    loss2 = SpringIsingRelaxedEnergy.apply(to_dev(J), to_dev(x0), None, dt.detach(), z, 10)
+    assert float(loss2) == L
