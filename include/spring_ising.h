@@ -107,8 +107,12 @@ typedef struct {
   int32_t order;      /* si_order */
   int32_t wall;       /* si_wall */
   int32_t precision;  /* si_precision */
-  int32_t tile;       /* 0 = automatic kernel choice; otherwise a tile id
-                         reported by spring_ising_info (tuning override) */
+  int32_t tile;       /* 0 = automatic kernel choice (the process's tile
+                         cache when it holds this context's key, else the
+                         built-in preference order); otherwise a tile id
+                         reported by spring_ising_info (tuning override).
+                         A batch takes 0, 1 (128 x 64 work items) or 2
+                         (64 x 64). */
   int32_t energy_every; /* E >= 0.  E > 0: in-run energy checks.  After every
                          step that brings the step index t to a multiple of E,
                          the Eq. (1) energies of all replicas' spins are
@@ -119,6 +123,14 @@ typedef struct {
                          inside captured HIP graphs.  The paper follows the
                          energy over the iterations (Fig. 4).  0 = off. */
 } si_params;
+
+/* Where the step kernel's tile of a context came from (si_info.tile_source). */
+typedef enum {
+  SI_TILE_FROM_TABLE = 0,   /* built-in preference order (from tile sweeps) */
+  SI_TILE_FROM_CACHE = 1,   /* the process's tile cache (see tile_cache_load) */
+  SI_TILE_FROM_CALLER = 2,  /* si_params.tile */
+  SI_TILE_FROM_AUTOTUNE = 3 /* an autotune call on this context */
+} si_tile_source;
 
 /* Read-only facts about a context (host struct). */
 typedef struct {
@@ -137,6 +149,8 @@ typedef struct {
   int32_t resident_steps;   /* run() calls of at least this many steps use the
                                resident launch (0: off or not available) */
   int32_t resident_groups;  /* workgroups of that launch (0: not available) */
+  int32_t tile_source;      /* si_tile_source of `tile` */
+  int32_t n_inst;           /* instances of a batch (0: single instance) */
 } si_info;
 
 /* Fill *prm (host) with the paper's parameter values and total_steps = S. */
@@ -169,13 +183,15 @@ si_status spring_ising_init(si_ctx **out, int32_t n, int32_t r, const float *J,
  *   x0: host array of n_inst device pointers, instance i r*n[i] floats.
  *   p0: host array of n_inst device pointers (instance i r*n[i] floats, or
  *       NULL for zero momenta of that instance), or NULL: all momenta 0.
- * Precisions: FP32 (128x64 tiles, instances padded to 128), or the BF16 forms
- * BF16X_FP8J (every J exact in FP8), BF16X_HILOJ and BF16X_MIXEDJ (FP8 J
- * where exact, hi + lo BF16 J otherwise), on 128x64 tiles with instances
- * padded to 128; BF16X_BF16J and BF16X3_EXACTJ: SI_ERR_UNSUPPORTED.  Each
- * instance's trajectory equals the single-instance run of the same form on
- * the 64x64 tile of that slab depth (FP32: tile 14; FP8 J: BF16 tile 9;
- * hi + lo: BF16 tile 7) bit for bit.  In every later call the
+ * Precisions: FP32, or the BF16 forms BF16X_FP8J (every J exact in FP8),
+ * BF16X_HILOJ and BF16X_MIXEDJ (FP8 J where exact, hi + lo BF16 J
+ * otherwise), with instances padded to 128; BF16X_BF16J and BF16X3_EXACTJ:
+ * SI_ERR_UNSUPPORTED.  Work items of 128 x 64 (batch tile 1) or 64 x 64
+ * (batch tile 2): prm->tile, else the tile cache's entry for this batch's
+ * key, else tile 1; autotune times both.  Each instance's trajectory equals
+ * the single-instance run of the same form on the 64x64 tile of that slab
+ * depth (FP32: tile 14; FP8 J: BF16 tile 9; hi + lo: BF16 tile 7) bit for
+ * bit, with either batch tile.  In every later call the
  * instances are concatenated: state/spin arrays hold instance i's r*n[i]
  * values (replica-major) at offset r * (n[0] + ... + n[i-1]); energies hold
  * instance i's r values at offset r*i.  set_field and
@@ -248,13 +264,39 @@ si_status spring_ising_set_ksplit(si_ctx *ctx, int32_t ksplit);
 si_status spring_ising_set_resident(si_ctx *ctx, int32_t min_steps);
 
 /* Autotuner: time `steps` steps of every step kernel that can serve this
- * context (its precision and padded shape), starting from the current state,
- * restore the state after each candidate, and keep the fastest for later
- * steps.  *best_tile and *best_us (host, nullable) receive the choice and its
- * time per step.  Kernels with a different MFMA shape add the contraction in
- * a different order, so later trajectories may differ in the last bits.
- * Synchronises once per candidate. */
+ * context (its precision and padded shape; on a batch, both batch tiles),
+ * starting from the current state, restore the state after each candidate,
+ * and keep the fastest for later steps.  The choice is also stored in the
+ * process's tile cache under this context's key, so that later contexts of
+ * that key created with tile 0 start on it.  *best_tile and *best_us (host,
+ * nullable) receive the choice and its time per step.  Kernels with a
+ * different MFMA shape add the contraction in a different order, so later
+ * trajectories may differ in the last bits (the two batch tiles never do).
+ * Synchronises once per candidate.  The paper streams the replicas of
+ * independent tests through one feature map (Methods, hardware
+ * implementation); the tile that maps them best is measured here. */
 si_status spring_ising_autotune(si_ctx *ctx, int32_t steps, int32_t *best_tile, float *best_us);
+
+/* Tile cache of the process (shared by every context and thread).  Key:
+ *   single instance: (precision, N-bucket, R rounded up to 64, CU count);
+ *   batch: (precision, bucket of the sum of the padded N_i, bucket of the
+ *          largest padded N_i, R rounded up to 64, CU count);
+ * the N-bucket of x is b with 2^(b-1) < x <= 2^b.  Value: tile id and its
+ * time per step.  autotune writes it; init and init_batch with tile 0 read
+ * it.  The file form is text:
+ *   line 1: "# spring_ising tile cache 1"
+ *   line 2: "build <build id>"
+ *   then one line per entry: "<kind> <precision> <nb> <mb> <r64> <cus>
+ *   <tile> <us>" (kind 0: single instance, mb 0; kind 1: batch).
+ * save writes every entry (SI_ERR_INVALID if the file cannot be written).
+ * load merges a file's entries into the cache and sets *n_loaded (host,
+ * nullable): SI_ERR_INVALID, with nothing loaded, for a file that does not
+ * parse or names a tile that cannot serve its key; SI_ERR_STATE, with
+ * nothing loaded, for a file written by another build (tile ids may differ).
+ * clear empties the cache. */
+si_status spring_ising_tile_cache_save(const char *path);
+si_status spring_ising_tile_cache_load(const char *path, int32_t *n_loaded);
+si_status spring_ising_tile_cache_clear(void);
 
 /* Readout: s[r*n + i] = +1 if q_i >= 0 (also -0.0), else -1 (device int8). */
 si_status spring_ising_spins(si_ctx *ctx, int8_t *s);

@@ -99,14 +99,17 @@ hipError_t launch_resident_f32(int32_t tile, const StepArgs &a, const ResidentAr
                                hipStream_t s);
 
 // Batched form: per-instance buffers and the work list of one grouped launch.
+// Batch tiles (both precisions): 1 = 128 x 64 work items, 2 = 64 x 64.
 constexpr int BATCH_BM = 128, BATCH_BN = 64;
+constexpr int32_t BATCH_TILE_LAST = 2;
+inline int32_t batch_tile_rows(int32_t btile) { return btile == 2 ? 64 : 128; }
 struct BatchDesc {
   const float *J;         // [n_pad][n_pad]
   float *q0, *q1, *p0, *p1;  // [r_pad][n_pad] ping-pong state
   int32_t n_pad, n;
 };
 hipError_t launch_step_batch_f32(const StepArgs &a, const BatchDesc *descs, const int4 *items,
-                                 int32_t n_items, int32_t cur, hipStream_t s);
+                                 int32_t n_items, int32_t cur, int32_t btile, hipStream_t s);
 
 // Step on the BF16 matrix cores (precision forms).
 constexpr int32_t TILE_BF16_LAST = 33;
@@ -127,8 +130,8 @@ struct BStepArgs {
 hipError_t launch_step_bf16(int32_t tile, int32_t precision, const BStepArgs &a, hipStream_t s);
 // Batched precision form: per-instance J format (fmt 1: FP8 e4m3, 2: hi + lo
 // BF16), BF16 plane of q per instance; instances padded to 128 (FP8 slabs
-// are 128 deep), work items of 128 rows.  `base` carries the schedules,
-// constants and r_pad.
+// are 128 deep), work items of the batch tile's rows.  `base` carries the
+// schedules, constants and r_pad.
 constexpr int BATCH_BF16_NPAD = 128, BATCH_BF16_BM = 128;
 struct BBatchDesc {
   const void *Ja, *Jb;
@@ -137,7 +140,7 @@ struct BBatchDesc {
   int32_t n_pad, fmt;
 };
 hipError_t launch_step_batch_bf16(const BStepArgs &base, const BBatchDesc *descs,
-                                  const int4 *items, int32_t n_items, int32_t cur,
+                                  const int4 *items, int32_t n_items, int32_t cur, int32_t btile,
                                   hipStream_t s);
 bool tile_valid_bf16(int32_t tile, int32_t precision);
 hipError_t launch_pack_j_lowp(const float *J, int64_t total, int32_t precision, void *out_a,

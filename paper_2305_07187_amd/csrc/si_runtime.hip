@@ -7,7 +7,10 @@
 #include <string.h>
 
 #include <new>
+#include <map>
+#include <mutex>
 #include <string>
+#include <tuple>
 #include <algorithm>
 #include <vector>
 
@@ -95,6 +98,7 @@ struct si_ctx {
   bool poisoned = false;
   int32_t inject_countdown = 0;  // test hook: > 0 fails the n-th checked HIP call
   uint16_t *tune_qb = nullptr;    // autotune: saved BF16 planes of q
+  float *tune_save = nullptr;     // autotune of a batch: saved q and p
   hipEvent_t tune_ev[2] = {nullptr, nullptr};
   int64_t bytes = 0;
   std::vector<void *> allocs;
@@ -140,6 +144,8 @@ struct si_ctx {
   // split contraction: 0 = automatic, >= 1 = forced number of k ranges
   int32_t ksplit_mode = 0;
   int32_t user_tile = 0;        // tile requested at init (0: automatic)
+  int32_t tile_source = SI_TILE_FROM_TABLE;
+  int64_t b_items_cap = 0;      // int4 entries of the device work list
   float *fsplit = nullptr;      // partial products of the split contraction
   int64_t fsplit_cap = 0;       // floats
   int32_t *res_sync = nullptr;  // [0] time-out flag, [64 ..] per-group step counts
@@ -404,6 +410,84 @@ static hipError_t init_energy_checks(si_ctx *c) {
 #endif
 static const char k_build_id[] = "SI_BUILD_ID:" SI_BUILD_ID;
 
+// The process's tile cache: (kind, precision, N-bucket, largest-N bucket,
+// R rounded to 64, CU count) -> (tile, us per step).  Kind 0: single
+// instance (largest-N bucket 0), kind 1: batch.
+namespace {
+using TileKey = std::tuple<int32_t, int32_t, int32_t, int32_t, int32_t, int32_t>;
+struct TileEntry {
+  int32_t tile;
+  float us;
+};
+std::mutex g_tile_mu;
+std::map<TileKey, TileEntry> g_tile_cache;
+
+int32_t n_bucket(int64_t x) {
+  int32_t b = 0;
+  while (b < 62 && ((int64_t)1 << b) < x) ++b;
+  return b;
+}
+
+TileKey tile_key(const si_ctx *c) {
+  if (c->n_inst) {
+    int64_t rows = 0;
+    for (int32_t np : c->b_npad) rows += np;
+    return TileKey{1, c->prm.precision, n_bucket(rows), n_bucket(c->b_max_npad),
+                   (int32_t)round_up(c->r, 64), c->num_cus};
+  }
+  return TileKey{0, c->prm.precision, n_bucket(c->n), 0, (int32_t)round_up(c->r, 64),
+                 c->num_cus};
+}
+
+// Can `tile` serve contexts of this key at all (padding aside)?
+bool tile_serves(int32_t kind, int32_t precision, int32_t tile) {
+  if (kind == 1) return tile >= 1 && tile <= BATCH_TILE_LAST;
+  if (precision == SI_PREC_FP32) return tile >= 1 && tile <= TILE_F32_LAST;
+  return tile >= 1 && tile <= TILE_BF16_LAST && tile_valid_bf16(tile, precision);
+}
+
+bool tile_cache_get(const TileKey &k, int32_t *tile) {
+  std::lock_guard<std::mutex> lock(g_tile_mu);
+  auto it = g_tile_cache.find(k);
+  if (it == g_tile_cache.end()) return false;
+  *tile = it->second.tile;
+  return true;
+}
+
+void tile_cache_put(const TileKey &k, int32_t tile, float us) {
+  std::lock_guard<std::mutex> lock(g_tile_mu);
+  g_tile_cache[k] = TileEntry{tile, us};
+}
+
+const char k_cache_magic[] = "# spring_ising tile cache 1";
+}  // namespace
+
+// Work list of a batch for its tile (instance, row tile, column tile),
+// longest contraction first, uploaded to the device list.
+static hipError_t batch_items(si_ctx *c) {
+  std::vector<int32_t> order(c->n_inst);
+  for (int32_t i = 0; i < c->n_inst; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int32_t x, int32_t y) { return c->b_npad[x] > c->b_npad[y]; });
+  const int32_t rows = batch_tile_rows(c->tile);
+  c->b_items_host.clear();
+  for (int32_t i : order)
+    for (int32_t rt = 0; rt < c->b_npad[i] / rows; ++rt)
+      for (int32_t ct = 0; ct < c->r_pad / BATCH_BN; ++ct) c->b_items_host.push_back(int4{i, rt, ct, 0});
+  if ((int64_t)c->b_items_host.size() > c->b_items_cap) {
+    hipError_t e = c->alloc(&c->b_items, (int64_t)c->b_items_host.size());
+    if (e != hipSuccess) return e;
+    c->b_items_cap = (int64_t)c->b_items_host.size();
+  }
+  hipError_t e = hipMemcpyAsync(c->b_items, c->b_items_host.data(),
+                                sizeof(int4) * c->b_items_host.size(), hipMemcpyHostToDevice,
+                                c->stream);
+  // the host list may change before an asynchronous copy from pageable
+  // memory has read it
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  return e;
+}
+
 extern "C" {
 
 const char *spring_ising_last_error(void) { return g_last_error.c_str(); }
@@ -510,9 +594,20 @@ si_status spring_ising_init(si_ctx **out, int32_t n, int32_t r, const float *J, 
 
   const bool lowp = prm->precision != SI_PREC_FP32;
   c->user_tile = prm->tile;
-  c->tile = prm->tile ? prm->tile
-                      : (lowp ? choose_tile_bf16(n, r, c->num_cus, prm->precision)
-                              : choose_tile(n, r, c->num_cus));
+  c->n = n;
+  c->r = r;
+  int32_t cached = 0;
+  if (prm->tile) {
+    c->tile = prm->tile;
+    c->tile_source = SI_TILE_FROM_CALLER;
+  } else if (tile_cache_get(tile_key(c), &cached) &&
+             tile_serves(0, prm->precision, cached)) {
+    c->tile = cached;
+    c->tile_source = SI_TILE_FROM_CACHE;
+  } else {
+    c->tile = lowp ? choose_tile_bf16(n, r, c->num_cus, prm->precision)
+                   : choose_tile(n, r, c->num_cus);
+  }
   if (lowp && !tile_valid_bf16(c->tile, prm->precision)) {
     const int32_t bad = c->tile;
     delete c;
@@ -585,7 +680,9 @@ si_status spring_ising_init_batch(si_ctx **out, int32_t n_inst, const int32_t *n
   if (st != SI_OK) return st;
   if (prm->precision == SI_PREC_BF16X_BF16J || prm->precision == SI_PREC_BF16X3_EXACTJ)
     return fail(SI_ERR_UNSUPPORTED, "init_batch: precision %d has no batched form", prm->precision);
-  if (prm->tile != 0) return fail(SI_ERR_INVALID, "init_batch: the batch uses fixed tiles");
+  if (prm->tile < 0 || prm->tile > BATCH_TILE_LAST)
+    return fail(SI_ERR_INVALID, "init_batch: batch tile %d not in 0..%d", prm->tile,
+                BATCH_TILE_LAST);
   const bool lowp = prm->precision != SI_PREC_FP32;
   for (int32_t i = 0; i < n_inst; ++i) {
     if (n[i] < 1 || n[i] > 65536) return fail(SI_ERR_INVALID, "init_batch: n[%d]=%d", i, n[i]);
@@ -737,15 +834,26 @@ si_status spring_ising_init_batch(si_ctx **out, int32_t n_inst, const int32_t *n
       c->bb_desc_host[i] = d;
     }
   }
-  // work list, longest contraction first
+  // batch tile: the caller's, else the tile cache's, else 128-row items
+  int32_t cached = 0;
+  if (prm->tile) {
+    c->tile = prm->tile;
+    c->tile_source = SI_TILE_FROM_CALLER;
+  } else if (tile_cache_get(tile_key(c), &cached) && tile_serves(1, prm->precision, cached)) {
+    c->tile = cached;
+    c->tile_source = SI_TILE_FROM_CACHE;
+  } else {
+    c->tile = 1;
+  }
+  // the device work list holds the longest list (64-row items)
+  int64_t items_max = 0;
+  for (int32_t i = 0; i < n_inst; ++i) items_max += (int64_t)(c->b_npad[i] / 64) * (c->r_pad / BATCH_BN);
+  BINIT_HIP(c->alloc(&c->b_items, items_max));
+  c->b_items_cap = items_max;
   std::vector<int32_t> order(n_inst);
   for (int32_t i = 0; i < n_inst; ++i) order[i] = i;
   std::stable_sort(order.begin(), order.end(),
                    [&](int32_t x, int32_t y) { return c->b_npad[x] > c->b_npad[y]; });
-  const int32_t item_rows = lowp ? BATCH_BF16_BM : BATCH_BM;
-  for (int32_t i : order)
-    for (int32_t rt = 0; rt < c->b_npad[i] / item_rows; ++rt)
-      for (int32_t ct = 0; ct < c->r_pad / BATCH_BN; ++ct) c->b_items_host.push_back(int4{i, rt, ct, 0});
   // grouped energy: exact int32 where the couplings are integer and the sum
   // cannot overflow, else the FP32 coupling sum; 64 x 64 tiles
   c->eb_desc_host.resize(n_inst);
@@ -771,7 +879,6 @@ si_status spring_ising_init_batch(si_ctx **out, int32_t n_inst, const int32_t *n
                            sizeof(int4) * c->eb_items_host.size(), hipMemcpyHostToDevice,
                            c->stream));
   BINIT_HIP(c->alloc(&c->b_desc, n_inst));
-  BINIT_HIP(c->alloc(&c->b_items, (int64_t)c->b_items_host.size()));
   BINIT_HIP(hipMemcpyAsync(c->b_desc, c->b_desc_host.data(), sizeof(BatchDesc) * n_inst,
                            hipMemcpyHostToDevice, c->stream));
   if (lowp) {
@@ -779,8 +886,7 @@ si_status spring_ising_init_batch(si_ctx **out, int32_t n_inst, const int32_t *n
     BINIT_HIP(hipMemcpyAsync(c->bb_desc, c->bb_desc_host.data(), sizeof(BBatchDesc) * n_inst,
                              hipMemcpyHostToDevice, c->stream));
   }
-  BINIT_HIP(hipMemcpyAsync(c->b_items, c->b_items_host.data(),
-                           sizeof(int4) * c->b_items_host.size(), hipMemcpyHostToDevice, c->stream));
+  BINIT_HIP(batch_items(c));
   build_schedules(*prm, c->host_dt, c->host_zeta);
   BINIT_HIP(hipMemcpyAsync(c->dt, c->host_dt.data(), sizeof(float) * prm->total_steps,
                            hipMemcpyHostToDevice, c->stream));
@@ -928,7 +1034,8 @@ static si_status do_steps_batch(si_ctx *c, int32_t n_steps) {
     for (int32_t s = 0; s < n_steps; ++s) {
       b.t = c->t;
       SI_HIP(c, launch_step_batch_bf16(b, c->bb_desc, c->b_items,
-                                       (int32_t)c->b_items_host.size(), c->cur, c->stream));
+                                       (int32_t)c->b_items_host.size(), c->cur, c->tile,
+                                       c->stream));
       c->cur ^= 1;
       c->t += 1;
       SI_ENERGY_CHECK(c);
@@ -939,7 +1046,7 @@ static si_status do_steps_batch(si_ctx *c, int32_t n_steps) {
   for (int32_t s = 0; s < n_steps; ++s) {
     a.t = c->t;
     SI_HIP(c, launch_step_batch_f32(a, c->b_desc, c->b_items, (int32_t)c->b_items_host.size(),
-                                    c->cur, c->stream));
+                                    c->cur, c->tile, c->stream));
     c->cur ^= 1;
     c->t += 1;
     SI_ENERGY_CHECK(c);
@@ -1282,13 +1389,72 @@ static bool tile_launchable(const si_ctx *c, int32_t tile) {
 // candidate (one host synchronisation per candidate).  Candidates are
 // filtered on the host before anything is launched; once a candidate has
 // been launched, any HIP failure poisons the context like everywhere else.
+// Autotune of a batch: both batch tiles, timed from the current state of
+// every instance, which is restored after each.
+static si_status autotune_batch(si_ctx *c, int32_t steps, int32_t *best_tile, float *best_us) {
+  const int64_t S = c->b_stot;
+  if (!c->tune_save) SI_HIP(c, c->alloc(&c->tune_save, 2 * S));
+  if (c->b_lowp && !c->tune_qb) SI_HIP(c, c->alloc(&c->tune_qb, S));
+  const int32_t t0 = c->t, cur0 = c->cur, tile0 = c->tile;
+  float *q0 = c->b_q[cur0][0], *p0 = c->b_p[cur0][0];
+  uint16_t *qb0 = c->b_lowp ? c->b_qb[cur0][0] : nullptr;
+  SI_HIP(c, hipMemcpyAsync(c->tune_save, q0, S * 4, hipMemcpyDeviceToDevice, c->stream));
+  SI_HIP(c, hipMemcpyAsync(c->tune_save + S, p0, S * 4, hipMemcpyDeviceToDevice, c->stream));
+  if (qb0) SI_HIP(c, hipMemcpyAsync(c->tune_qb, qb0, S * 2, hipMemcpyDeviceToDevice, c->stream));
+  if (!c->tune_ev[0]) {
+    SI_HIP(c, hipEventCreate(&c->tune_ev[0]));
+    SI_HIP(c, hipEventCreate(&c->tune_ev[1]));
+  }
+  hipEvent_t e0 = c->tune_ev[0], e1 = c->tune_ev[1];
+  struct KeepEvery {
+    si_ctx *c;
+    int32_t v;
+    ~KeepEvery() { c->e_every = v; }
+  } keep{c, c->e_every};
+  c->e_every = 0;
+  const int32_t timed = steps - 1 > 0 ? steps - 1 : 1;
+  int32_t best = tile0;
+  float best_t = 1e30f;
+  for (int32_t tile = 1; tile <= BATCH_TILE_LAST; ++tile) {
+    c->tile = tile;
+    SI_HIP(c, batch_items(c));
+    si_status st = do_steps(c, 1);  // warm-up
+    if (st != SI_OK) return st;
+    SI_HIP(c, hipEventRecord(e0, c->stream));
+    st = do_steps(c, timed);
+    if (st != SI_OK) return st;
+    SI_HIP(c, hipEventRecord(e1, c->stream));
+    SI_HIP(c, hipMemcpyAsync(q0, c->tune_save, S * 4, hipMemcpyDeviceToDevice, c->stream));
+    SI_HIP(c, hipMemcpyAsync(p0, c->tune_save + S, S * 4, hipMemcpyDeviceToDevice, c->stream));
+    if (qb0) SI_HIP(c, hipMemcpyAsync(qb0, c->tune_qb, S * 2, hipMemcpyDeviceToDevice, c->stream));
+    c->t = t0;
+    c->cur = cur0;
+    SI_HIP(c, hipEventSynchronize(e1));
+    float ms = 0.f;
+    SI_HIP(c, hipEventElapsedTime(&ms, e0, e1));
+    const float us = 1000.f * ms / (float)timed;
+    if (us < best_t) {
+      best_t = us;
+      best = tile;
+    }
+  }
+  c->tile = best;
+  SI_HIP(c, batch_items(c));
+  c->tile_source = SI_TILE_FROM_AUTOTUNE;
+  c->drop_graphs();
+  tile_cache_put(tile_key(c), best, best_t);
+  if (best_tile) *best_tile = best;
+  if (best_us) *best_us = best_t;
+  return SI_OK;
+}
+
 si_status spring_ising_autotune(si_ctx *c, int32_t steps, int32_t *best_tile, float *best_us) {
   SI_USABLE(c);
   if (steps < 1) return fail(SI_ERR_INVALID, "autotune: steps < 1");
-  if (c->n_inst) return fail(SI_ERR_UNSUPPORTED, "autotune: not available for a batch");
   if ((int64_t)c->t + steps > c->prm.total_steps)
     return fail(SI_ERR_RANGE, "autotune: %d steps from t=%d exceed total_steps", steps, c->t);
   c->epoch++;
+  if (c->n_inst) return autotune_batch(c, steps, best_tile, best_us);
   const int64_t NR = (int64_t)c->n_pad * c->r_pad;
   // saved state: q and p in the adjoint's segment buffer, the BF16 planes of
   // q in a buffer of their own; both kept for later calls
@@ -1358,6 +1524,8 @@ si_status spring_ising_autotune(si_ctx *c, int32_t steps, int32_t *best_tile, fl
   c->tile = best;
   SI_HIP(c, ensure_split_ws(c));
   c->drop_graphs();
+  c->tile_source = SI_TILE_FROM_AUTOTUNE;
+  tile_cache_put(tile_key(c), best, best_t);
   if (best_tile) *best_tile = best;
   if (best_us) *best_us = best_t;
   return SI_OK;
@@ -1584,6 +1752,90 @@ si_status spring_ising_set_state(si_ctx *c, const float *x, const float *p, int3
   return SI_OK;
 }
 
+si_status spring_ising_tile_cache_save(const char *path) {
+  if (!path) return fail(SI_ERR_INVALID, "tile_cache_save: path is null");
+  std::map<TileKey, TileEntry> snap;
+  {
+    std::lock_guard<std::mutex> lock(g_tile_mu);
+    snap = g_tile_cache;
+  }
+  FILE *f = fopen(path, "w");
+  if (!f) return fail(SI_ERR_INVALID, "tile_cache_save: cannot write %s", path);
+  fprintf(f, "%s\nbuild %s\n", k_cache_magic, spring_ising_build_id());
+  for (const auto &kv : snap) {
+    const TileKey &k = kv.first;
+    fprintf(f, "%d %d %d %d %d %d %d %.9g\n", std::get<0>(k), std::get<1>(k), std::get<2>(k),
+            std::get<3>(k), std::get<4>(k), std::get<5>(k), kv.second.tile, (double)kv.second.us);
+  }
+  const bool ok = !ferror(f);
+  if (fclose(f) != 0 || !ok) return fail(SI_ERR_INVALID, "tile_cache_save: write to %s failed", path);
+  return SI_OK;
+}
+
+si_status spring_ising_tile_cache_load(const char *path, int32_t *n_loaded) {
+  if (n_loaded) *n_loaded = 0;
+  if (!path) return fail(SI_ERR_INVALID, "tile_cache_load: path is null");
+  FILE *f = fopen(path, "r");
+  if (!f) return fail(SI_ERR_INVALID, "tile_cache_load: cannot read %s", path);
+  char line[256];
+  std::map<TileKey, TileEntry> got;
+  si_status st = SI_OK;
+  int lineno = 0;
+  while (fgets(line, sizeof line, f)) {
+    ++lineno;
+    const size_t len = strlen(line);
+    if (len && line[len - 1] == '\n') line[len - 1] = 0;
+    if (lineno == 1) {
+      if (strcmp(line, k_cache_magic) != 0) {
+        st = fail(SI_ERR_INVALID, "tile_cache_load: %s is not a tile cache", path);
+        break;
+      }
+      continue;
+    }
+    if (lineno == 2) {
+      char id[64];
+      if (sscanf(line, "build %63s", id) != 1) {
+        st = fail(SI_ERR_INVALID, "tile_cache_load: %s line 2: no build id", path);
+        break;
+      }
+      if (strcmp(id, spring_ising_build_id()) != 0) {
+        st = fail(SI_ERR_STATE, "tile_cache_load: %s was written by build %s, this is %s", path,
+                  id, spring_ising_build_id());
+        break;
+      }
+      continue;
+    }
+    if (!line[0]) continue;
+    int v[7];
+    float us;
+    char extra;
+    if (sscanf(line, "%d %d %d %d %d %d %d %f %c", &v[0], &v[1], &v[2], &v[3], &v[4], &v[5],
+               &v[6], &us, &extra) != 8 ||
+        (v[0] != 0 && v[0] != 1) || v[1] < SI_PREC_FP32 || v[1] > SI_PREC_BF16X_MIXEDJ ||
+        v[2] < 0 || v[3] < 0 || v[4] < 64 || v[4] % 64 || v[5] < 1 ||
+        !tile_serves(v[0], v[1], v[6])) {
+      st = fail(SI_ERR_INVALID, "tile_cache_load: %s line %d: bad entry", path, lineno);
+      break;
+    }
+    got[TileKey{v[0], v[1], v[2], v[3], v[4], v[5]}] = TileEntry{v[6], us};
+  }
+  if (st == SI_OK && lineno < 2) st = fail(SI_ERR_INVALID, "tile_cache_load: %s is incomplete", path);
+  fclose(f);
+  if (st != SI_OK) return st;
+  {
+    std::lock_guard<std::mutex> lock(g_tile_mu);
+    for (const auto &kv : got) g_tile_cache[kv.first] = kv.second;
+  }
+  if (n_loaded) *n_loaded = (int32_t)got.size();
+  return SI_OK;
+}
+
+si_status spring_ising_tile_cache_clear(void) {
+  std::lock_guard<std::mutex> lock(g_tile_mu);
+  g_tile_cache.clear();
+  return SI_OK;
+}
+
 si_status spring_ising_info(si_ctx *c, si_info *info) {
   if (!c || !info) return fail(SI_ERR_INVALID, "info: null argument");
   memset(info, 0, sizeof *info);
@@ -1602,6 +1854,8 @@ si_status spring_ising_info(si_ctx *c, si_info *info) {
   info->j_fp8_exact = c->hflags[4] == 0;
   info->j_bf16_exact = c->hflags[5] == 0;
   info->tile = c->tile;
+  info->tile_source = c->tile_source;
+  info->n_inst = c->n_inst;
   info->precision = c->prm.precision;
   info->graph_steps = c->graph_min_steps;
   info->device_bytes = c->bytes;
@@ -1609,8 +1863,7 @@ si_status spring_ising_info(si_ctx *c, si_info *info) {
   info->resident_steps = info->resident_groups ? c->resident_min_steps : 0;
   if (c->n_inst)
     snprintf(info->kernel_name, sizeof info->kernel_name, "step_batch_%s_%dx%d_x%d",
-             c->b_lowp ? "bf16" : "f32", c->b_lowp ? BATCH_BF16_BM : BATCH_BM, BATCH_BN,
-             c->n_inst);
+             c->b_lowp ? "bf16" : "f32", batch_tile_rows(c->tile), BATCH_BN, c->n_inst);
   else if (split_for(c, c->tile) > 1)
     snprintf(info->kernel_name, sizeof info->kernel_name, "%s_ks%d",
              shape_of(c->prm.precision, c->tile).name, split_for(c, c->tile));

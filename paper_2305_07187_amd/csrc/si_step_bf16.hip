@@ -649,26 +649,29 @@ __global__ __launch_bounds__(C::NTT) void step_bf16_dma_kernel(BStepArgs a) {
 }
 
 // Batched precision form: one launch advances every instance by one step.
-// Work item (instance, row tile, column tile) as in the FP32 batch, with
-// 128-row tiles; each instance carries its own J format: FP8 e4m3 (J exact
-// in FP8) with 128-deep slabs, hi + lo BF16 otherwise with 64-deep slabs.
-// Eight waves of 32x32, the wave tile and slab depth of the 64x64
-// single-instance tiles of those formats, so every instance matches its
-// standalone run on those tiles bit for bit.  The batch streams J from HBM
-// once per step; the 128-row tile halves the re-reads of the BF16 q plane
-// per byte of J against 64 rows (3.6 % less time per step on the 256-
-// instance workload).
-using BatchFp8Cfg = Bf16DmaCfg<BATCH_BF16_BM, BATCH_BN, 4, 2, 128, 1, 1, 3>;
-using BatchHiloCfg = Bf16DmaCfg<BATCH_BF16_BM, BATCH_BN, 4, 2, 64, 2, 1, 3>;
-static_assert(BatchFp8Cfg::NT == BatchHiloCfg::NT, "one block shape for both formats");
-constexpr int BATCH_BF16_LDS = BatchFp8Cfg::LDS_BYTES > BatchHiloCfg::LDS_BYTES
-                                   ? BatchFp8Cfg::LDS_BYTES
-                                   : BatchHiloCfg::LDS_BYTES;
+// Work item (instance, row tile, column tile) as in the FP32 batch; each
+// instance carries its own J format: FP8 e4m3 (J exact in FP8) with 128-deep
+// slabs, hi + lo BF16 otherwise with 64-deep slabs.  Two tile heights, picked
+// per batch: 128 rows (eight waves of 32x32) or 64 rows (four waves).  Both
+// have the wave tile and slab depth of the 64x64 single-instance tiles of
+// those formats, so every instance matches its standalone run on those tiles
+// bit for bit.  The batch streams J from HBM once per step; the 128-row tile
+// halves the re-reads of the BF16 q plane per byte of J against 64 rows
+// (3.6 % less time per step on the 256-instance workload), the 64-row tile
+// gives twice the work items to batches too small to fill the chip.
+template <int BM>
+struct BatchBf16Tiles {
+  using Fp8 = Bf16DmaCfg<BM, BATCH_BN, BM / 32, 2, 128, 1, 1, 3>;
+  using Hilo = Bf16DmaCfg<BM, BATCH_BN, BM / 32, 2, 64, 2, 1, 3>;
+  static_assert(Fp8::NT == Hilo::NT, "one block shape for both formats");
+  static constexpr int LDS = Fp8::LDS_BYTES > Hilo::LDS_BYTES ? Fp8::LDS_BYTES : Hilo::LDS_BYTES;
+};
 
-template <int ORDER, int WALL>
-__global__ __launch_bounds__(BatchFp8Cfg::NT) void step_batch_bf16_kernel(
+template <int BM, int ORDER, int WALL>
+__global__ __launch_bounds__(BatchBf16Tiles<BM>::Fp8::NT) void step_batch_bf16_kernel(
     BStepArgs base, const BBatchDesc *__restrict__ descs, const int4 *__restrict__ items, int cur) {
-  __shared__ __attribute__((aligned(16))) uint8_t smem[BATCH_BF16_LDS];
+  using T = BatchBf16Tiles<BM>;
+  __shared__ __attribute__((aligned(16))) uint8_t smem[T::LDS];
   const int4 it = items[blockIdx.x];
   const BBatchDesc d = descs[it.x];
   BStepArgs a = base;
@@ -687,24 +690,35 @@ __global__ __launch_bounds__(BatchFp8Cfg::NT) void step_batch_bf16_kernel(
   a.plane_stride = (int64_t)d.n_pad * base.r_pad;
   a.h = nullptr;
   if (d.fmt == 1)
-    bf16_dma_tile<BatchFp8Cfg, ORDER, WALL>(a, it.y * BATCH_BF16_BM, it.z * BATCH_BN, smem);
+    bf16_dma_tile<typename T::Fp8, ORDER, WALL>(a, it.y * BM, it.z * BATCH_BN, smem);
   else
-    bf16_dma_tile<BatchHiloCfg, ORDER, WALL>(a, it.y * BATCH_BF16_BM, it.z * BATCH_BN, smem);
+    bf16_dma_tile<typename T::Hilo, ORDER, WALL>(a, it.y * BM, it.z * BATCH_BN, smem);
 }
 
-hipError_t launch_step_batch_bf16(const BStepArgs &base, const BBatchDesc *descs,
-                                  const int4 *items, int32_t n_items, int32_t cur,
-                                  hipStream_t s) {
-  if (n_items <= 0) return hipSuccess;
-  dim3 grid(n_items), block(BatchFp8Cfg::NT);
+template <int BM>
+static hipError_t launch_batch_bf16_bm(const BStepArgs &base, const BBatchDesc *descs,
+                                       const int4 *items, int32_t n_items, int32_t cur,
+                                       hipStream_t s) {
+  dim3 grid(n_items), block(BatchBf16Tiles<BM>::Fp8::NT);
   switch (base.order * 2 + base.wall) {
-    case 0: step_batch_bf16_kernel<SI_ORDER_PAPER, SI_WALL_CLAMP><<<grid, block, 0, s>>>(base, descs, items, cur); break;
-    case 1: step_batch_bf16_kernel<SI_ORDER_PAPER, SI_WALL_INELASTIC><<<grid, block, 0, s>>>(base, descs, items, cur); break;
-    case 2: step_batch_bf16_kernel<SI_ORDER_SYMPLECTIC, SI_WALL_CLAMP><<<grid, block, 0, s>>>(base, descs, items, cur); break;
-    case 3: step_batch_bf16_kernel<SI_ORDER_SYMPLECTIC, SI_WALL_INELASTIC><<<grid, block, 0, s>>>(base, descs, items, cur); break;
+    case 0: step_batch_bf16_kernel<BM, SI_ORDER_PAPER, SI_WALL_CLAMP><<<grid, block, 0, s>>>(base, descs, items, cur); break;
+    case 1: step_batch_bf16_kernel<BM, SI_ORDER_PAPER, SI_WALL_INELASTIC><<<grid, block, 0, s>>>(base, descs, items, cur); break;
+    case 2: step_batch_bf16_kernel<BM, SI_ORDER_SYMPLECTIC, SI_WALL_CLAMP><<<grid, block, 0, s>>>(base, descs, items, cur); break;
+    case 3: step_batch_bf16_kernel<BM, SI_ORDER_SYMPLECTIC, SI_WALL_INELASTIC><<<grid, block, 0, s>>>(base, descs, items, cur); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+hipError_t launch_step_batch_bf16(const BStepArgs &base, const BBatchDesc *descs,
+                                  const int4 *items, int32_t n_items, int32_t cur, int32_t btile,
+                                  hipStream_t s) {
+  if (n_items <= 0) return hipSuccess;
+  switch (btile) {
+    case 1: return launch_batch_bf16_bm<BATCH_BF16_BM>(base, descs, items, n_items, cur, s);
+    case 2: return launch_batch_bf16_bm<64>(base, descs, items, n_items, cur, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 template <class C>

@@ -319,23 +319,37 @@ hipError_t launch_resident_f32(int32_t tile, const StepArgs &a, const ResidentAr
   }
 }
 
-// Batched tiles: 128 x 64 (eight waves of 32 x 32), 32x32x2 MFMA, direct-to-LDS
-// ring (4 stages); the same contraction order as every single-instance
-// direct-to-LDS tile with one accumulator chain.
+// Batched tiles, picked per batch (the autotuner times both): 128 x 64
+// (eight waves of 32 x 32) or 64 x 64 (four waves; the configuration of
+// single-instance tile 14), 32x32x2 MFMA over a 4-stage direct-to-LDS ring.
+// Both have the contraction order of every single-instance direct-to-LDS tile
+// with one accumulator chain, so the pick never changes a result.
 using BatchCfg = F32Cfg<BATCH_BM, BATCH_BN, 4, 2, 32, 32, 4, 1>;
+using BatchCfg64 = F32Cfg<64, BATCH_BN, 2, 2, 32, 32, 4, 1>;
 
-hipError_t launch_step_batch_f32(const StepArgs &a, const BatchDesc *descs, const int4 *items,
-                                 int32_t n_items, int32_t cur, hipStream_t s) {
-  if (n_items <= 0) return hipSuccess;
-  dim3 grid(n_items), block(BatchCfg::NT);
+template <class C>
+static hipError_t launch_batch_cfg(const StepArgs &a, const BatchDesc *descs, const int4 *items,
+                                   int32_t n_items, int32_t cur, hipStream_t s) {
+  dim3 grid(n_items), block(C::NT);
   switch (a.order * 2 + a.wall) {
-    case 0: step_batch_f32_kernel<BatchCfg, SI_ORDER_PAPER, SI_WALL_CLAMP><<<grid, block, 0, s>>>(a, descs, items, cur); break;
-    case 1: step_batch_f32_kernel<BatchCfg, SI_ORDER_PAPER, SI_WALL_INELASTIC><<<grid, block, 0, s>>>(a, descs, items, cur); break;
-    case 2: step_batch_f32_kernel<BatchCfg, SI_ORDER_SYMPLECTIC, SI_WALL_CLAMP><<<grid, block, 0, s>>>(a, descs, items, cur); break;
-    case 3: step_batch_f32_kernel<BatchCfg, SI_ORDER_SYMPLECTIC, SI_WALL_INELASTIC><<<grid, block, 0, s>>>(a, descs, items, cur); break;
+    case 0: step_batch_f32_kernel<C, SI_ORDER_PAPER, SI_WALL_CLAMP><<<grid, block, 0, s>>>(a, descs, items, cur); break;
+    case 1: step_batch_f32_kernel<C, SI_ORDER_PAPER, SI_WALL_INELASTIC><<<grid, block, 0, s>>>(a, descs, items, cur); break;
+    case 2: step_batch_f32_kernel<C, SI_ORDER_SYMPLECTIC, SI_WALL_CLAMP><<<grid, block, 0, s>>>(a, descs, items, cur); break;
+    case 3: step_batch_f32_kernel<C, SI_ORDER_SYMPLECTIC, SI_WALL_INELASTIC><<<grid, block, 0, s>>>(a, descs, items, cur); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+hipError_t launch_step_batch_f32(const StepArgs &a, const BatchDesc *descs, const int4 *items,
+                                 int32_t n_items, int32_t cur, int32_t btile, hipStream_t s) {
+  if (n_items <= 0) return hipSuccess;
+  static_assert(BatchCfg::BM == 128 && BatchCfg64::BM == 64, "batch tile rows");
+  switch (btile) {
+    case 1: return launch_batch_cfg<BatchCfg>(a, descs, items, n_items, cur, s);
+    case 2: return launch_batch_cfg<BatchCfg64>(a, descs, items, n_items, cur, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 hipError_t launch_step_f32(int32_t tile, const StepArgs &a, hipStream_t s) {

@@ -57,6 +57,7 @@ class si_info(ctypes.Structure):
         ("precision", ctypes.c_int32), ("graph_steps", ctypes.c_int32),
         ("device_bytes", ctypes.c_int64), ("kernel_name", ctypes.c_char * 64),
         ("resident_steps", ctypes.c_int32), ("resident_groups", ctypes.c_int32),
+        ("tile_source", ctypes.c_int32), ("n_inst", ctypes.c_int32),
     ]
 
     def as_dict(self):
@@ -91,6 +92,9 @@ _SIGNATURES = {
     "spring_ising_info": [_P, ctypes.POINTER(si_info)],
     "spring_ising_relaxed_energy_grad": [_P, _I, _P, _P, _P],
     "spring_ising_relaxed_energy_forward": [_P, _I, _P],
+    "spring_ising_tile_cache_save": [ctypes.c_char_p],
+    "spring_ising_tile_cache_load": [ctypes.c_char_p, ctypes.POINTER(_I)],
+    "spring_ising_tile_cache_clear": [],
     "spring_ising_relaxed_energy_backward": [_P, _P, _P],
     "spring_ising_set_graph": [_P, _I],
     "spring_ising_set_resident": [_P, _I],
@@ -356,6 +360,23 @@ def spring_ising_autotune(ctx, steps):
     return tile.value, us.value
 
 
+TILE_SOURCES = {0: "table", 1: "cache", 2: "caller", 3: "autotune"}
+
+
+def spring_ising_tile_cache_save(path):
+    _check(load_library().spring_ising_tile_cache_save(os.fsencode(path)))
+
+
+def spring_ising_tile_cache_load(path):
+    n = ctypes.c_int32()
+    _check(load_library().spring_ising_tile_cache_load(os.fsencode(path), ctypes.byref(n)))
+    return n.value
+
+
+def spring_ising_tile_cache_clear():
+    _check(load_library().spring_ising_tile_cache_clear())
+
+
 def spring_ising_info(ctx) -> dict:
     info = si_info()
     _check(load_library().spring_ising_info(ctx, ctypes.byref(info)))
@@ -413,6 +434,11 @@ class SpringIsingBatch:
 
     def set_graph(self, min_steps):
         spring_ising_set_graph(self.ctx, min_steps)
+
+    def autotune(self, steps=5):
+        """Time both batch tiles from the current state; keep and cache the
+        faster.  Returns (tile, us per step)."""
+        return spring_ising_autotune(self.ctx, steps)
 
     def _split(self, flat):
         return [flat[self.offsets[i]:self.offsets[i + 1]].view(self.r, n)

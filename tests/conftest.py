@@ -28,3 +28,13 @@ def pytest_collection_modifyitems(config, items):
     for item in items:
         if "gpu" in item.keywords:
             item.add_marker(skip)
+
+
+@pytest.fixture(autouse=True)
+def _fresh_tile_cache():
+    # autotune fills the process-wide tile cache, which later contexts with
+    # automatic tiles would read: every test starts and ends with it empty
+    yield
+    si = sys.modules.get("paper_2305_07187_amd.spring_ising")
+    if si is not None and si._lib is not None:
+        si.spring_ising_tile_cache_clear()

@@ -59,7 +59,7 @@ def test_header_compiles_standalone(tmp_path, std, compiler):
 
 def test_struct_layouts_match_binding():
     assert ctypes.sizeof(si.si_params) == 56
-    assert ctypes.sizeof(si.si_info) == 4 * 12 + 8 + 64 + 4 * 2
+    assert ctypes.sizeof(si.si_info) == 4 * 12 + 8 + 64 + 4 * 4
 
 
 def test_default_params_are_the_papers():

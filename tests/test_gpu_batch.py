@@ -22,12 +22,16 @@ def _batch(specs, S, r=R, **kw):
     return b, Js, xs
 
 
-def test_batch_equals_standalone_runs():
+@pytest.mark.parametrize("btile", [1, 2])
+def test_batch_equals_standalone_runs(btile):
     import torch
     si = ensure_built()
-    announce("batch vs standalone, bit for bit")
+    announce(f"batch (tile {btile}) vs standalone, bit for bit")
     S = 300
-    b, Js, xs = _batch(SIZES, S)
+    b, Js, xs = _batch(SIZES, S, tile=btile)
+    info = b.info()
+    assert info["tile"] == btile and si.TILE_SOURCES[info["tile_source"]] == "caller"
+    assert info["kernel_name"].startswith(f"step_batch_f32_{128 if btile == 1 else 64}x64")
     b.run(200)
     xb, pb, t = b.state()
     eb = b.energy()
@@ -199,13 +203,14 @@ def test_batch_full_workload_generated_on_device():
 FORM_TILE = {"pm1": ("bf16x_fp8j", 9), "gauss": ("bf16x_hiloj", 7)}
 
 
-def test_bf16_batch_equals_standalone_runs():
+@pytest.mark.parametrize("btile", [1, 2])
+def test_bf16_batch_equals_standalone_runs(btile):
     import torch
     si = ensure_built()
-    announce("BF16 batch (FP8 / hi+lo per instance) vs standalone runs, bit for bit")
+    announce(f"BF16 batch (tile {btile}; FP8 / hi+lo per instance) vs standalone runs, bit for bit")
     S = 300
-    b, Js, xs = _batch(SIZES, S, precision="bf16x_mixedj")
-    assert b.info()["kernel_name"].startswith("step_batch_bf16")
+    b, Js, xs = _batch(SIZES, S, precision="bf16x_mixedj", tile=btile)
+    assert b.info()["kernel_name"].startswith(f"step_batch_bf16_{128 if btile == 1 else 64}x64")
     b.run(150)
     xb, pb, t = b.state()
     eb = b.energy(exact=False)
@@ -347,3 +352,50 @@ def test_bf16_batch_full_workload_vs_fp32():
              f"max |z| {np.abs(z).max():.2f}")
     assert abs(z.mean()) < 0.35 and z.std() < 1.4 and (np.abs(z) > 4).mean() < 0.02
     assert res["bf16x_mixedj"][1] < res["fp32"][1]
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x_mixedj"])
+def test_batch_autotune_fills_the_tile_cache(precision, tmp_path):
+    import torch
+    si = ensure_built()
+    announce(f"batch autotune and tile cache ({precision})")
+    si.spring_ising_tile_cache_clear()
+    S = 60
+    specs = SIZES[:4]
+    b, Js, xs = _batch(specs, S, precision=precision)
+    assert si.TILE_SOURCES[b.info()["tile_source"]] == "table" and b.info()["tile"] == 1
+    b.run(10)
+    tile, us = b.autotune(4)
+    assert tile in (1, 2) and us > 0
+    info = b.info()
+    assert info["tile"] == tile and si.TILE_SOURCES[info["tile_source"]] == "autotune"
+    assert info["t"] == 10
+    b.run(20)
+    xb, pb, t = b.state()
+    torch.cuda.synchronize()
+    # the state was restored after every candidate: same as an untuned run
+    ref, _, _ = _batch(specs, S, precision=precision, tile=1)
+    ref.run(30)
+    xr, pr, _ = ref.state()
+    torch.cuda.synchronize()
+    for i in range(len(specs)):
+        assert np.array_equal(xb[i].cpu().numpy(), xr[i].cpu().numpy()), i
+        assert np.array_equal(pb[i].cpu().numpy(), pr[i].cpu().numpy()), i
+    ref.close()
+    # a new batch of the same key starts on the cached tile
+    b2, _, _ = _batch(specs, S, precision=precision)
+    assert b2.info()["tile"] == tile and si.TILE_SOURCES[b2.info()["tile_source"]] == "cache"
+    b2.close()
+    # the cache survives a save / clear / load round trip
+    path = tmp_path / "tiles.txt"
+    si.spring_ising_tile_cache_save(str(path))
+    si.spring_ising_tile_cache_clear()
+    b3, _, _ = _batch(specs, S, precision=precision)
+    assert si.TILE_SOURCES[b3.info()["tile_source"]] == "table"
+    b3.close()
+    assert si.spring_ising_tile_cache_load(str(path)) == 1
+    b4, _, _ = _batch(specs, S, precision=precision)
+    assert b4.info()["tile"] == tile and si.TILE_SOURCES[b4.info()["tile_source"]] == "cache"
+    b4.close()
+    b.close()
+    si.spring_ising_tile_cache_clear()

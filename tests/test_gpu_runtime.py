@@ -91,6 +91,19 @@ def test_autotune_keeps_state_and_parity(precision):
     assert info["tile"] == tile and us > 0
     assert t_after == t_before == 3
     assert torch.equal(x_before, x_after) and torch.equal(p_before, p_after)
+    assert si.TILE_SOURCES[info["tile_source"]] == "autotune"
+    # later contexts of the same key (precision, N-bucket, R) start on the
+    # tuned tile; N = 120 shares N = 100's bucket (64, 128]
+    for nn in (100, 120):
+        m2 = si.SpringIsing(to_dev(instances.make_pm1(nn, 1)), to_dev(instances.make_x0(nn, r, 1)),
+                            total_steps=S, precision=precision)
+        assert m2.info()["tile"] == tile, nn
+        assert si.TILE_SOURCES[m2.info()["tile_source"]] == "cache", nn
+        m2.close()
+    m3 = si.SpringIsing(to_dev(instances.make_pm1(200, 1)), to_dev(instances.make_x0(200, r, 1)),
+                        total_steps=S, precision=precision)
+    assert si.TILE_SOURCES[m3.info()["tile_source"]] == "table"  # another bucket
+    m3.close()
     if precision == "fp32":
         m.run(47)
         x, _, _ = m.state()
