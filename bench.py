@@ -166,7 +166,16 @@ def batched_form(si, steps=300, n_inst=256, r=64, sequential=True, time_to_targe
     out = {"workload": f"{n_inst} instances, N uniform in [64, 4096] (sum {sum(n for n, _, _ in recipe)}), "
                        f"half +-1 half Gaussian, R={r}", "steps_timed": steps}
     for form in ("fp32", "bf16x_mixedj"):
+        # the autotuner picks the batch tile on a context of its own; the
+        # timed context (and the time-to-target runs) read it from the cache
+        tb = si.SpringIsingBatch(Js, xs, total_steps=20, precision=form)
+        tile, us = tb.autotune(6)
+        tb.close()
         b = si.SpringIsingBatch(Js, xs, total_steps=steps + 10, precision=form)
+        info = b.info()
+        out[f"{form}_tile"] = {"autotuned": tile, "autotune_us": round(us, 1),
+                               "used": info["tile"],
+                               "source": si.TILE_SOURCES[info["tile_source"]]}
         b.run(10)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -184,6 +193,15 @@ def batched_form(si, steps=300, n_inst=256, r=64, sequential=True, time_to_targe
         b.run(steps)
         torch.cuda.synchronize()
         out[f"{form}_batched_graph_ms_per_step"] = 1000.0 * (time.perf_counter() - t0) / steps
+        # where the step's time goes: two traced steps (CU busy share of the
+        # step, the tail after the first CU runs out of work, the gap between
+        # the two launches)
+        rec, mhz = b.timeline(2)
+        st = si.batch_timeline_stats(rec, mhz)
+        out[f"{form}_timeline"] = {
+            "span_us": round(st[0]["span_us"], 1), "cu_busy_mean": round(st[0]["cu_busy_mean"], 4),
+            "cu_busy_min": round(st[0]["cu_busy_min"], 4), "tail_us": round(st[0]["tail_us"], 1),
+            "launch_gap_us": round(st[0]["gap_to_next_us"], 2)}
         b.close()
     if time_to_target:
         ref_xs = [instances.make_x0_torch(n, r, seed ^ 0x5A5A5A5A, device=dev)

@@ -277,6 +277,22 @@ si_status spring_ising_set_resident(si_ctx *ctx, int32_t min_steps);
  * implementation); the tile that maps them best is measured here. */
 si_status spring_ising_autotune(si_ctx *ctx, int32_t steps, int32_t *best_tile, float *best_us);
 
+/* Timeline of the batched step (tracing of the grouped launch that runs the
+ * paper's independent tests side by side, Fig. 3): runs n_steps steps (1..16)
+ * of a batch exactly as run() does, and records for every work item of every
+ * step when its workgroup started and ended on the device's real-time clock
+ * and which CU ran it.  The results are bit-identical to run(n_steps).
+ *   out      : host, at least n_steps * (work items) records of 4 uint64:
+ *              {start, end, CU, step << 32 | item}, step-major; CU is
+ *              XCC_ID << 16 | bits 15:8 of the wave's HW_ID register.
+ *   cap      : records out holds; *n_records (host, nullable) receives the
+ *              count needed, also when cap is too small (SI_ERR_INVALID).
+ *   clock_mhz: host, nullable: the clock's rate.
+ * SI_ERR_UNSUPPORTED on a single-instance context, SI_ERR_RANGE past the
+ * schedule.  Synchronises once. */
+si_status spring_ising_batch_timeline(si_ctx *ctx, int32_t n_steps, uint64_t *out, int64_t cap,
+                                      int64_t *n_records, double *clock_mhz);
+
 /* Tile cache of the process (shared by every context and thread).  Key:
  *   single instance: (precision, N-bucket, R rounded up to 64, CU count);
  *   batch: (precision, bucket of the sum of the padded N_i, bucket of the

@@ -108,8 +108,11 @@ struct BatchDesc {
   float *q0, *q1, *p0, *p1;  // [r_pad][n_pad] ping-pong state
   int32_t n_pad, n;
 };
+// trace: null, or n_items records of 4 words written by the launch (see
+// batch_trace_record).
 hipError_t launch_step_batch_f32(const StepArgs &a, const BatchDesc *descs, const int4 *items,
-                                 int32_t n_items, int32_t cur, int32_t btile, hipStream_t s);
+                                 int32_t n_items, int32_t cur, int32_t btile,
+                                 unsigned long long *trace, hipStream_t s);
 
 // Step on the BF16 matrix cores (precision forms).
 constexpr int32_t TILE_BF16_LAST = 33;
@@ -141,7 +144,7 @@ struct BBatchDesc {
 };
 hipError_t launch_step_batch_bf16(const BStepArgs &base, const BBatchDesc *descs,
                                   const int4 *items, int32_t n_items, int32_t cur, int32_t btile,
-                                  hipStream_t s);
+                                  unsigned long long *trace, hipStream_t s);
 bool tile_valid_bf16(int32_t tile, int32_t precision);
 hipError_t launch_pack_j_lowp(const float *J, int64_t total, int32_t precision, void *out_a,
                               void *out_b, hipStream_t s);

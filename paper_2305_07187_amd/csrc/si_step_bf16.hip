@@ -21,6 +21,7 @@
 // one 128-bit LDS load, identically for A and B, so the product sums every
 // index exactly once.
 #include "si_epilogue.h"
+#include "si_trace.h"
 #include "si_internal.h"
 
 namespace si {
@@ -669,7 +670,9 @@ struct BatchBf16Tiles {
 
 template <int BM, int ORDER, int WALL>
 __global__ __launch_bounds__(BatchBf16Tiles<BM>::Fp8::NT) void step_batch_bf16_kernel(
-    BStepArgs base, const BBatchDesc *__restrict__ descs, const int4 *__restrict__ items, int cur) {
+    BStepArgs base, const BBatchDesc *__restrict__ descs, const int4 *__restrict__ items, int cur,
+    unsigned long long *trace) {
+  const unsigned long long start = wall_clock64();
   using T = BatchBf16Tiles<BM>;
   __shared__ __attribute__((aligned(16))) uint8_t smem[T::LDS];
   const int4 it = items[blockIdx.x];
@@ -693,18 +696,19 @@ __global__ __launch_bounds__(BatchBf16Tiles<BM>::Fp8::NT) void step_batch_bf16_k
     bf16_dma_tile<typename T::Fp8, ORDER, WALL>(a, it.y * BM, it.z * BATCH_BN, smem);
   else
     bf16_dma_tile<typename T::Hilo, ORDER, WALL>(a, it.y * BM, it.z * BATCH_BN, smem);
+  if (trace) batch_trace_record(trace, start);
 }
 
 template <int BM>
 static hipError_t launch_batch_bf16_bm(const BStepArgs &base, const BBatchDesc *descs,
                                        const int4 *items, int32_t n_items, int32_t cur,
-                                       hipStream_t s) {
+                                       unsigned long long *trace, hipStream_t s) {
   dim3 grid(n_items), block(BatchBf16Tiles<BM>::Fp8::NT);
   switch (base.order * 2 + base.wall) {
-    case 0: step_batch_bf16_kernel<BM, SI_ORDER_PAPER, SI_WALL_CLAMP><<<grid, block, 0, s>>>(base, descs, items, cur); break;
-    case 1: step_batch_bf16_kernel<BM, SI_ORDER_PAPER, SI_WALL_INELASTIC><<<grid, block, 0, s>>>(base, descs, items, cur); break;
-    case 2: step_batch_bf16_kernel<BM, SI_ORDER_SYMPLECTIC, SI_WALL_CLAMP><<<grid, block, 0, s>>>(base, descs, items, cur); break;
-    case 3: step_batch_bf16_kernel<BM, SI_ORDER_SYMPLECTIC, SI_WALL_INELASTIC><<<grid, block, 0, s>>>(base, descs, items, cur); break;
+    case 0: step_batch_bf16_kernel<BM, SI_ORDER_PAPER, SI_WALL_CLAMP><<<grid, block, 0, s>>>(base, descs, items, cur, trace); break;
+    case 1: step_batch_bf16_kernel<BM, SI_ORDER_PAPER, SI_WALL_INELASTIC><<<grid, block, 0, s>>>(base, descs, items, cur, trace); break;
+    case 2: step_batch_bf16_kernel<BM, SI_ORDER_SYMPLECTIC, SI_WALL_CLAMP><<<grid, block, 0, s>>>(base, descs, items, cur, trace); break;
+    case 3: step_batch_bf16_kernel<BM, SI_ORDER_SYMPLECTIC, SI_WALL_INELASTIC><<<grid, block, 0, s>>>(base, descs, items, cur, trace); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -712,11 +716,11 @@ static hipError_t launch_batch_bf16_bm(const BStepArgs &base, const BBatchDesc *
 
 hipError_t launch_step_batch_bf16(const BStepArgs &base, const BBatchDesc *descs,
                                   const int4 *items, int32_t n_items, int32_t cur, int32_t btile,
-                                  hipStream_t s) {
+                                  unsigned long long *trace, hipStream_t s) {
   if (n_items <= 0) return hipSuccess;
   switch (btile) {
-    case 1: return launch_batch_bf16_bm<BATCH_BF16_BM>(base, descs, items, n_items, cur, s);
-    case 2: return launch_batch_bf16_bm<64>(base, descs, items, n_items, cur, s);
+    case 1: return launch_batch_bf16_bm<BATCH_BF16_BM>(base, descs, items, n_items, cur, trace, s);
+    case 2: return launch_batch_bf16_bm<64>(base, descs, items, n_items, cur, trace, s);
     default: return hipErrorInvalidValue;
   }
 }

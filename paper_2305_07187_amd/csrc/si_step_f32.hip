@@ -22,6 +22,7 @@
 // s-th of them; each index is summed exactly once, in increasing kk order,
 // so the permutation only changes which lane holds which index.
 #include "si_epilogue.h"
+#include "si_trace.h"
 #include "si_f32_gemm.h"
 
 namespace si {
@@ -221,13 +222,16 @@ template <class C, int ORDER, int WALL>
 __global__ __launch_bounds__(C::NT) void step_batch_f32_kernel(StepArgs a,
                                                                const BatchDesc *__restrict__ descs,
                                                                const int4 *__restrict__ items,
-                                                               int cur) {
+                                                               int cur,
+                                                               unsigned long long *trace) {
+  const unsigned long long start = wall_clock64();
   __shared__ __attribute__((aligned(16))) float smem[C::LDS_FLOATS];
   const int4 it = items[blockIdx.x];
   const BatchDesc d = descs[it.x];
   step_tile<C, ORDER, WALL>(a, d.J, cur ? d.q1 : d.q0, cur ? d.p1 : d.p0, cur ? d.q0 : d.q1,
                             cur ? d.p0 : d.p1, d.n_pad, kdim<C>(d.n, d.n_pad), it.y * C::BM,
                             it.z * C::BN, smem);
+  if (trace) batch_trace_record(trace, start);
 }
 
 TileShape tile_shape(int32_t tile) {
@@ -329,25 +333,27 @@ using BatchCfg64 = F32Cfg<64, BATCH_BN, 2, 2, 32, 32, 4, 1>;
 
 template <class C>
 static hipError_t launch_batch_cfg(const StepArgs &a, const BatchDesc *descs, const int4 *items,
-                                   int32_t n_items, int32_t cur, hipStream_t s) {
+                                   int32_t n_items, int32_t cur, unsigned long long *trace,
+                                   hipStream_t s) {
   dim3 grid(n_items), block(C::NT);
   switch (a.order * 2 + a.wall) {
-    case 0: step_batch_f32_kernel<C, SI_ORDER_PAPER, SI_WALL_CLAMP><<<grid, block, 0, s>>>(a, descs, items, cur); break;
-    case 1: step_batch_f32_kernel<C, SI_ORDER_PAPER, SI_WALL_INELASTIC><<<grid, block, 0, s>>>(a, descs, items, cur); break;
-    case 2: step_batch_f32_kernel<C, SI_ORDER_SYMPLECTIC, SI_WALL_CLAMP><<<grid, block, 0, s>>>(a, descs, items, cur); break;
-    case 3: step_batch_f32_kernel<C, SI_ORDER_SYMPLECTIC, SI_WALL_INELASTIC><<<grid, block, 0, s>>>(a, descs, items, cur); break;
+    case 0: step_batch_f32_kernel<C, SI_ORDER_PAPER, SI_WALL_CLAMP><<<grid, block, 0, s>>>(a, descs, items, cur, trace); break;
+    case 1: step_batch_f32_kernel<C, SI_ORDER_PAPER, SI_WALL_INELASTIC><<<grid, block, 0, s>>>(a, descs, items, cur, trace); break;
+    case 2: step_batch_f32_kernel<C, SI_ORDER_SYMPLECTIC, SI_WALL_CLAMP><<<grid, block, 0, s>>>(a, descs, items, cur, trace); break;
+    case 3: step_batch_f32_kernel<C, SI_ORDER_SYMPLECTIC, SI_WALL_INELASTIC><<<grid, block, 0, s>>>(a, descs, items, cur, trace); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
 hipError_t launch_step_batch_f32(const StepArgs &a, const BatchDesc *descs, const int4 *items,
-                                 int32_t n_items, int32_t cur, int32_t btile, hipStream_t s) {
+                                 int32_t n_items, int32_t cur, int32_t btile,
+                                 unsigned long long *trace, hipStream_t s) {
   if (n_items <= 0) return hipSuccess;
   static_assert(BatchCfg::BM == 128 && BatchCfg64::BM == 64, "batch tile rows");
   switch (btile) {
-    case 1: return launch_batch_cfg<BatchCfg>(a, descs, items, n_items, cur, s);
-    case 2: return launch_batch_cfg<BatchCfg64>(a, descs, items, n_items, cur, s);
+    case 1: return launch_batch_cfg<BatchCfg>(a, descs, items, n_items, cur, trace, s);
+    case 2: return launch_batch_cfg<BatchCfg64>(a, descs, items, n_items, cur, trace, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -95,6 +95,8 @@ _SIGNATURES = {
     "spring_ising_tile_cache_save": [ctypes.c_char_p],
     "spring_ising_tile_cache_load": [ctypes.c_char_p, ctypes.POINTER(_I)],
     "spring_ising_tile_cache_clear": [],
+    "spring_ising_batch_timeline": [_P, _I, _P, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64),
+                                    ctypes.POINTER(ctypes.c_double)],
     "spring_ising_relaxed_energy_backward": [_P, _P, _P],
     "spring_ising_set_graph": [_P, _I],
     "spring_ising_set_resident": [_P, _I],
@@ -363,6 +365,61 @@ def spring_ising_autotune(ctx, steps):
 TILE_SOURCES = {0: "table", 1: "cache", 2: "caller", 3: "autotune"}
 
 
+def spring_ising_batch_timeline(ctx, n_steps):
+    """Run n_steps traced steps of a batch; returns (records uint64 [k, 4]:
+    start, end, CU, step << 32 | item; clock rate in MHz)."""
+    import numpy as np
+    lib = load_library()
+    need = ctypes.c_int64()
+    mhz = ctypes.c_double()
+    st = lib.spring_ising_batch_timeline(ctx, int(n_steps), None, 0, ctypes.byref(need), None)
+    if need.value == 0:
+        _check(st)
+    out = np.zeros((need.value, 4), dtype=np.uint64)
+    _check(lib.spring_ising_batch_timeline(ctx, int(n_steps), out.ctypes.data, need.value,
+                                           ctypes.byref(need), ctypes.byref(mhz)))
+    return out, mhz.value
+
+
+def batch_timeline_stats(records, clock_mhz):
+    """Per-step figures of a batch timeline: span (first start to last end),
+    the CUs' mean and least busy share of the span (a CU counts as busy while
+    any of its workgroups runs), the time from the first CU running out of
+    work to the end, and the gap to the next step's first start (us)."""
+    import numpy as np
+    steps = (records[:, 3] >> np.uint64(32)).astype(np.int64)
+    out = []
+    for s in np.unique(steps):
+        r = records[steps == s]
+        t0 = r[:, 0].astype(np.int64)
+        t1 = r[:, 1].astype(np.int64)
+        base = t0.min()
+        span = t1.max() - base
+        busy, ends = [], []
+        for cu in np.unique(r[:, 2]):
+            m = r[:, 2] == cu
+            iv = sorted(zip(t0[m], t1[m]))
+            tot, cs, ce = 0, iv[0][0], iv[0][1]
+            for a, b in iv[1:]:
+                if a > ce:
+                    tot += ce - cs
+                    cs, ce = a, b
+                else:
+                    ce = max(ce, b)
+            busy.append(tot + ce - cs)
+            ends.append(ce)
+        busy = np.array(busy, dtype=np.float64)
+        us = 1.0 / clock_mhz
+        out.append({"step": int(s), "span_us": span * us, "cus": len(busy),
+                    "cu_busy_mean": float(busy.mean() / span),
+                    "cu_busy_min": float(busy.min() / span),
+                    "tail_us": float((t1.max() - min(ends)) * us),
+                    "start": int(base), "end": int(t1.max())})
+    for a, b in zip(out, out[1:]):
+        a["gap_to_next_us"] = (b["start"] - a["end"]) / clock_mhz
+    return out
+
+
 def spring_ising_tile_cache_save(path):
     _check(load_library().spring_ising_tile_cache_save(os.fsencode(path)))
 
@@ -439,6 +496,11 @@ class SpringIsingBatch:
         """Time both batch tiles from the current state; keep and cache the
         faster.  Returns (tile, us per step)."""
         return spring_ising_autotune(self.ctx, steps)
+
+    def timeline(self, n_steps=2):
+        """n_steps traced steps: (records, clock MHz); see
+        spring_ising_batch_timeline."""
+        return spring_ising_batch_timeline(self.ctx, n_steps)
 
     def _split(self, flat):
         return [flat[self.offsets[i]:self.offsets[i + 1]].view(self.r, n)

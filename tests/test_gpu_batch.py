@@ -399,3 +399,56 @@ def test_batch_autotune_fills_the_tile_cache(precision, tmp_path):
     b4.close()
     b.close()
     si.spring_ising_tile_cache_clear()
+
+
+@pytest.mark.parametrize("precision,btile", [("fp32", 1), ("bf16x_mixedj", 2)])
+def test_batch_timeline(precision, btile):
+    import torch
+    si = ensure_built()
+    announce(f"batch timeline ({precision}, tile {btile})")
+    S = 40
+    b, Js, xs = _batch(SIZES, S, precision=precision, tile=btile)
+    b.run(5)
+    rec, mhz = b.timeline(3)
+    xb, pb, t = b.state()
+    torch.cuda.synchronize()
+    assert t == 8 and mhz > 0
+    rows = 128 if btile == 1 else 64
+    n_items = sum(((n + 127) // 128 * 128) // rows for n, _ in SIZES)
+    assert rec.shape == (3 * n_items, 4)
+    steps = (rec[:, 3] >> np.uint64(32)).astype(np.int64)
+    items = (rec[:, 3] & np.uint64(0xFFFFFFFF)).astype(np.int64)
+    ends = []
+    for s in range(3):
+        m = steps == s
+        assert np.array_equal(np.sort(items[m]), np.arange(n_items)), s
+        assert np.all(rec[m, 1] >= rec[m, 0])
+        if ends:
+            assert rec[m, 0].min() >= ends[-1]  # stream order: steps do not overlap
+        ends.append(rec[m, 1].max())
+    assert len(np.unique(rec[:, 2])) <= 256
+    stats = si.batch_timeline_stats(rec, mhz)
+    assert len(stats) == 3 and all(0 < st["cu_busy_mean"] <= 1 for st in stats)
+    # traced steps are ordinary steps
+    ref, _, _ = _batch(SIZES, S, precision=precision, tile=btile)
+    ref.run(8)
+    xr, pr, _ = ref.state()
+    torch.cuda.synchronize()
+    for i in range(len(SIZES)):
+        assert np.array_equal(xb[i].cpu().numpy(), xr[i].cpu().numpy()), i
+        assert np.array_equal(pb[i].cpu().numpy(), pr[i].cpu().numpy()), i
+    # argument rules
+    with pytest.raises(si.SpringIsingError) as e:
+        b.timeline(17)
+    assert e.value.status == si.SI_ERR_INVALID
+    b.run(S - 8)
+    with pytest.raises(si.SpringIsingError) as e:
+        b.timeline(1)
+    assert e.value.status == si.SI_ERR_RANGE
+    m = si.SpringIsing(to_dev(Js[0]), to_dev(xs[0]), total_steps=S)
+    with pytest.raises(si.SpringIsingError) as e:
+        si.spring_ising_batch_timeline(m.ctx, 1)
+    assert e.value.status == si.SI_ERR_UNSUPPORTED
+    m.close()
+    ref.close()
+    b.close()
