@@ -265,8 +265,9 @@ si_status spring_ising_set_resident(si_ctx *ctx, int32_t min_steps);
 
 /* Autotuner: time `steps` steps of every step kernel that can serve this
  * context (its precision and padded shape; on a batch, both batch tiles),
- * starting from the current state, restore the state after each candidate,
- * and keep the fastest for later steps.  The choice is also stored in the
+ * starting from the current state, in two rounds over all candidates (each
+ * candidate keeps its faster round), restore the state after each run, and
+ * keep the fastest for later steps.  The choice is also stored in the
  * process's tile cache under this context's key, so that later contexts of
  * that key created with tile 0 start on it.  *best_tile and *best_us (host,
  * nullable) receive the choice and its time per step.  Kernels with a

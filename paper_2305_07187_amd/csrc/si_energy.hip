@@ -111,7 +111,10 @@ __device__ __forceinline__ void energy_i8_tile(const int8_t *__restrict__ J8,
 // sum over them); the result D[8(v/4) + 4(l/32) + v%4][l%32] lands in
 // accumulator v < 16.  One 128 x 64 output tile per workgroup, eight waves of
 // 32 x 32, the J and S slabs (QBK contraction bytes deep) copied straight
-// into a three-slot LDS ring with the chunk swizzle of their rows.
+// into a three-slot LDS ring with the chunk swizzle of their rows.  With
+// ks > 1 the contraction is split over ks workgroups per tile, each adding
+// its part of s^T (J s) to the replica's integer accumulator (the field term
+// in part 0 only): integer sums, so the result does not depend on the order.
 // ---------------------------------------------------------------------------
 namespace {
 constexpr int QBM = 128, QBN = 64, QBK = 128, QST = 3, QNT = 512, QNW = QNT / 64;
@@ -136,13 +139,15 @@ __global__ __launch_bounds__(QNT) void energy_i8_kernel(const int8_t *__restrict
                                                         const int8_t *__restrict__ S8,
                                                         const int8_t *__restrict__ h8,
                                                         int32_t *__restrict__ acc_out, int ld,
-                                                        int r_pad) {
+                                                        int r_pad, int ks) {
   __shared__ __attribute__((aligned(16))) int8_t smem[QST * QSLOT];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wy = wave >> 1, wx = wave & 1;  // 4 x 2 waves of 32 x 32
   const int ncol = r_pad / QBN;
-  const int t = xcd_tile(blockIdx.x, gridDim.x);
+  const int u = xcd_tile(blockIdx.x, gridDim.x);
+  const int t = u / ks, part = u % ks;
   const int m0 = (t / ncol) * QBM, n0 = (t % ncol) * QBN;
+  const int nk = ld / QBK / ks, k0 = part * nk * QBK;  // this part's slabs
   // A wave-wide direct-to-LDS load writes 64 x 16 bytes: QRPD rows.  Lane
   // L fills position L % QCH of row L / QCH with the chunk that belongs
   // there (chunk c of row r is stored at position c ^ swz(r)).
@@ -152,12 +157,12 @@ __global__ __launch_bounds__(QNT) void energy_i8_kernel(const int8_t *__restrict
 #pragma unroll
   for (int d = 0; d < QAD; ++d) {
     const int row = (wave * QAD + d) * QRPD + drow;
-    srcA[d] = J8 + (size_t)(m0 + row) * ld + ((dch ^ lds_swz<QCH>(row)) << 4);
+    srcA[d] = J8 + (size_t)(m0 + row) * ld + k0 + ((dch ^ lds_swz<QCH>(row)) << 4);
   }
 #pragma unroll
   for (int d = 0; d < QBD; ++d) {
     const int row = (wave * QBD + d) * QRPD + drow;
-    srcB[d] = S8 + (size_t)(n0 + row) * ld + ((dch ^ lds_swz<QCH>(row)) << 4);
+    srcB[d] = S8 + (size_t)(n0 + row) * ld + k0 + ((dch ^ lds_swz<QCH>(row)) << 4);
   }
   auto issue = [&](int kt, int slot) {
     int8_t *st = smem + slot * QSLOT;
@@ -172,7 +177,6 @@ __global__ __launch_bounds__(QNT) void energy_i8_kernel(const int8_t *__restrict
                                        (lds_void_e *)(st + (QBM + (wave * QBD + d) * QRPD) * QBK),
                                        16, 0, 0);
   };
-  const int nk = ld / QBK;
 #pragma unroll
   for (int s = 0; s < QST - 1; ++s)
     if (s < nk) issue(s, s);
@@ -209,7 +213,7 @@ __global__ __launch_bounds__(QNT) void energy_i8_kernel(const int8_t *__restrict
     const int row = m0 + wy * 32 + g * 8 + h * 4;
     const char4 s4 = *reinterpret_cast<const char4 *>(S8 + (size_t)col * ld + row);
     char4 h4 = make_char4(0, 0, 0, 0);
-    if (h8) h4 = *reinterpret_cast<const char4 *>(h8 + row);
+    if (h8 && part == 0) h4 = *reinterpret_cast<const char4 *>(h8 + row);
     c += (int)s4.x * (acc[4 * g] + 2 * (int)h4.x);
     c += (int)s4.y * (acc[4 * g + 1] + 2 * (int)h4.y);
     c += (int)s4.z * (acc[4 * g + 2] + 2 * (int)h4.z);
@@ -282,10 +286,25 @@ hipError_t launch_sign(const float *q, int8_t *s8, int32_t n_pad, int32_t r_pad,
 }
 
 hipError_t launch_energy_i8(const int8_t *J8, const int8_t *S8, const int8_t *h8, int32_t *acc,
-                            int32_t n_pad, int32_t r_pad, hipStream_t s) {
-  if (n_pad % QBM || n_pad % QBK || r_pad % QBN) return hipErrorInvalidValue;
-  energy_i8_kernel<<<(n_pad / QBM) * (r_pad / QBN), QNT, 0, s>>>(J8, S8, h8, acc, n_pad, r_pad);
+                            int32_t n_pad, int32_t r_pad, int32_t ks, hipStream_t s) {
+  if (n_pad % QBM || n_pad % QBK || r_pad % QBN || ks < 1 || (n_pad / QBK) % ks)
+    return hipErrorInvalidValue;
+  energy_i8_kernel<<<(n_pad / QBM) * (r_pad / QBN) * ks, QNT, 0, s>>>(J8, S8, h8, acc, n_pad,
+                                                                      r_pad, ks);
   return hipGetLastError();
+}
+
+int32_t energy_i8_ksplit(int32_t n_pad, int32_t r_pad, int num_cus) {
+  const int64_t tiles = (int64_t)(n_pad / QBM) * (r_pad / QBN);
+  const int32_t nk = n_pad / QBK;
+  int32_t ks = 1;
+  // two workgroups fit a CU (72 KB of LDS each): split while the grid has
+  // fewer than that and every part keeps at least two slabs.  At N = 2000,
+  // R = 1024 (256 tiles) the readout took 15.6 us per call with 2 parts,
+  // 15.7 us unsplit, 20.1 and 30.7 us with 4 and 8 (more atomics per
+  // accumulator); the kernel waits on its slab loads, not on the matrix cores.
+  while (tiles * ks < 2 * (int64_t)num_cus && nk % (ks * 2) == 0 && nk / (ks * 2) >= 2) ks *= 2;
+  return ks;
 }
 
 hipError_t launch_energy_i8_finalize(int32_t *acc, int32_t r, int32_t *e_int, double *e_real,

@@ -191,7 +191,10 @@ hipError_t launch_fill_f64(double *p, int64_t count, double v, hipStream_t s);
 hipError_t launch_sign(const float *q, int8_t *s8, int32_t n_pad, int32_t r_pad,
                        hipStream_t s);
 hipError_t launch_energy_i8(const int8_t *J8, const int8_t *S8, const int8_t *h8,
-                            int32_t *acc, int32_t n_pad, int32_t r_pad, hipStream_t s);
+                            int32_t *acc, int32_t n_pad, int32_t r_pad, int32_t ks,
+                            hipStream_t s);
+// Contraction split of launch_energy_i8 for this shape (a power of two).
+int32_t energy_i8_ksplit(int32_t n_pad, int32_t r_pad, int num_cus);
 hipError_t launch_energy_i8_finalize(int32_t *acc, int32_t r, int32_t *e_int,
                                      double *e_real, hipStream_t s);
 hipError_t launch_zero_i32(int32_t *p, int64_t count, hipStream_t s);

@@ -1424,6 +1424,7 @@ static si_status autotune_batch(si_ctx *c, int32_t steps, int32_t *best_tile, fl
   const int32_t timed = steps - 1 > 0 ? steps - 1 : 1;
   int32_t best = tile0;
   float best_t = 1e30f;
+  for (int round = 0; round < 2; ++round)  // as for single instances
   for (int32_t tile = 1; tile <= BATCH_TILE_LAST; ++tile) {
     c->tile = tile;
     SI_HIP(c, batch_items(c));
@@ -1498,6 +1499,9 @@ si_status spring_ising_autotune(si_ctx *c, int32_t steps, int32_t *best_tile, fl
   const int32_t timed = steps - 1 > 0 ? steps - 1 : 1;
   int32_t best = tile0;
   float best_t = 1e30f;
+  // two rounds over the candidates, each keeping its faster round: the first
+  // candidates of a single round ran measurably slow (cold clocks and caches)
+  for (int round = 0; round < 2; ++round)
   for (int32_t tile = 1; tile <= last; ++tile) {
     if (!tile_launchable(c, tile)) continue;
     c->tile = tile;
@@ -1619,7 +1623,8 @@ static si_status energy_into(si_ctx *c, int32_t *e_int, double *e_real) {
   const int8_t *h8 = c->has_field ? c->h8 : nullptr;
   if (exact) {
     SI_HIP(c, launch_sign(c->q[c->cur], c->S8, c->n_pad, c->r_pad, c->stream));
-    SI_HIP(c, launch_energy_i8(c->J8, c->S8, h8, c->eacc, c->n_pad, c->r_pad, c->stream));
+    SI_HIP(c, launch_energy_i8(c->J8, c->S8, h8, c->eacc, c->n_pad, c->r_pad,
+                               energy_i8_ksplit(c->n_pad, c->r_pad, c->num_cus), c->stream));
     SI_HIP(c, launch_energy_i8_finalize(c->eacc, c->r, e_int, e_real, c->stream));
   } else {
     const float *hf = c->has_field ? c->hf : nullptr;
