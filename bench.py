@@ -434,8 +434,11 @@ def time_to_target(si, J, n, r, iters, every, stream, runs_per_form):
     the target, and the form's figure is the median over the seeds.  Equal
     final-energy distribution: a two-sample KS test of the pooled final
     energies (R x 5 seeds) against FP32's, and the difference of the means in
-    standard errors.  TTS99 = t_run ln(0.01) / ln(1 - P_s), P_s the pooled
-    fraction of replicas ending at or below the target."""
+    standard errors.  TTS99 takes one replica as a trial: P_s is the pooled
+    fraction of replicas ending at or below the target, a trial costs its
+    share t_run / R of a run of all R replicas together, and
+    TTS99 = (t_run / R) ln(0.01) / ln(1 - P_s).  P_run = 1 - (1 - P_s)^R is
+    the chance that a whole run reaches the target."""
     import math
 
     import numpy as np
@@ -477,17 +480,18 @@ def time_to_target(si, J, n, r, iters, every, stream, runs_per_form):
         med = ttts[len(ttts) // 2]
         p_s = float((fin <= target).mean())
         t_run = float(np.median([p["run_s"] for p in per_seed]))
+        t_trial = t_run / r
         if p_s >= 0.99:
-            tts99 = t_run
+            tts99 = t_trial
         elif p_s > 0:
-            tts99 = t_run * math.log(0.01) / math.log(1.0 - p_s)
+            tts99 = t_trial * math.log(0.01) / math.log(1.0 - p_s)
         else:
             tts99 = None
         forms[name] = {"kernel": kernel, "spin_updates_per_s": n * r * iters * runs_per_form / el_tot,
                        "avg_launch_us": us,
                        "ttt_median_s": med if math.isfinite(med) else None,
                        "per_seed": per_seed, "run_with_checks_s": t_run,
-                       "p_success": p_s, "tts99_s": tts99,
+                       "p_success": p_s, "p_run": 1.0 - (1.0 - p_s) ** r, "tts99_s": tts99,
                        "mean_energy": float(fin.mean()), "best_energy": float(fin.min())}
     t32 = forms["fp32"]["ttt_median_s"]
     for name in FORMS:
