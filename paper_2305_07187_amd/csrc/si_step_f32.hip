@@ -216,8 +216,8 @@ __global__ __launch_bounds__(C::NT) void resident_f32_kernel(StepArgs a, Residen
 }
 
 // Batched form: one launch advances every instance of a batch by one step.
-// Work item w = (instance, row tile, column tile); items are ordered by
-// decreasing contraction length so the longest tiles start first.
+// Work item w = (instance, row tile, column tile); the host orders the list
+// (whole instances per XCD, costliest items first on each).
 template <class C, int ORDER, int WALL>
 __global__ __launch_bounds__(C::NT) void step_batch_f32_kernel(StepArgs a,
                                                                const BatchDesc *__restrict__ descs,
