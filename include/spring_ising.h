@@ -406,7 +406,7 @@ si_status spring_ising_set_state(si_ctx *ctx, const float *x, const float *p, in
  *   dL_ddt, dL_dzeta: device, total_steps doubles each.
  * Supported for the paper order, clamping walls, FP32 precision and no
  * field; otherwise SI_ERR_UNSUPPORTED.  Allocates its workspace on first use
- * (about (ckpt_every + 1 + 2 (S - t0)/ckpt_every) state copies). */
+ * (about (C + 1 + 2 (S - t0)/C) state copies, C = min(ckpt_every, S - t0)). */
 si_status spring_ising_relaxed_energy_grad(si_ctx *ctx, int32_t ckpt_every, double *loss,
                                            double *dL_ddt, double *dL_dzeta);
 

@@ -1152,6 +1152,9 @@ static si_status adj_forward(si_ctx *c, int32_t C, double *loss) {
                 "FP32 precision and no field");
   c->tape.valid = false;
   const int32_t S = c->prm.total_steps, t0 = c->t;
+  // a segment never holds more than the remaining steps (the workspace is
+  // sized by the segment length)
+  if (C > S - t0) C = S - t0 > 0 ? S - t0 : 1;
   const int32_t nseg = (S - t0 + C - 1) / C;
   const int64_t NR = (int64_t)c->n_pad * c->r_pad;
   const int32_t asplit = adj_split(c);

@@ -350,3 +350,16 @@ def test_autograd_defers_the_sweep():
     # no schedule requires a gradient: the context is released in forward
     loss2 = SpringIsingRelaxedEnergy.apply(to_dev(J), to_dev(x0), None, dt.detach(), z, 10)
     assert float(loss2) == L
+
+
+def test_checkpoint_interval_beyond_the_schedule():
+    # an interval longer than the remaining steps is one segment (the
+    # workspace is sized by the segment, not by the requested interval)
+    announce("adjoint with a checkpoint interval past the schedule")
+    n, r, S = 100, 8, 40
+    J = instances.make_pm1(n, 5)
+    x0 = instances.make_x0(n, r, 5)
+    dt, zeta = _sched(1000, S)
+    a = _grad(J, x0, dt, zeta, ckpt=S)
+    b = _grad(J, x0, dt, zeta, ckpt=2 ** 30)
+    assert a[0] == b[0] and np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
