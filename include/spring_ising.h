@@ -153,7 +153,10 @@ typedef struct {
   int32_t n_inst;           /* instances of a batch (0: single instance) */
 } si_info;
 
-/* Fill *prm (host) with the paper's parameter values and total_steps = S. */
+/* Fill *prm (host) with the paper's parameter values and total_steps = S:
+ * k = 0.5, m = 1, Delta = 0.2 and zeta from 0.8 zeta0 to 10 zeta0 with
+ * zeta0 = 0.05 (Fig. 4 caption, Methods), the position wall sqrt 2
+ * (Eq. (6)) and the momentum wall 2 (Methods). */
 si_status spring_ising_default_params(si_params *prm, int32_t total_steps);
 
 /* Create a context for n spins and r replicas.
@@ -248,7 +251,7 @@ si_status spring_ising_set_graph(si_ctx *ctx, int32_t min_steps);
 si_status spring_ising_set_ksplit(si_ctx *ctx, int32_t ksplit);
 
 /* Execute run() calls of at least min_steps steps as one resident launch
- * (FP32 single instance; the per-step loop of Eq. 8 moved onto the device):
+ * (FP32 single instance; the per-step loop of Eq. (8) moved onto the device):
  * every workgroup owns one output tile for the whole call and keeps that
  * tile's q and p in registers, only q (which every other tile's coupling
  * product reads) passes through memory, and a grid-wide barrier separates
@@ -294,7 +297,8 @@ si_status spring_ising_autotune(si_ctx *ctx, int32_t steps, int32_t *best_tile, 
 si_status spring_ising_batch_timeline(si_ctx *ctx, int32_t n_steps, uint64_t *out, int64_t cap,
                                       int64_t *n_records, double *clock_mhz);
 
-/* Tile cache of the process (shared by every context and thread).  Key:
+/* Tile cache of the process (shared by every context and thread; library
+ * bookkeeping with no counterpart in the paper).  Key:
  *   single instance: (precision, N-bucket, R rounded up to 64, CU count);
  *   batch: (precision, bucket of the sum of the padded N_i, bucket of the
  *          largest padded N_i, R rounded up to 64, CU count);
@@ -315,7 +319,9 @@ si_status spring_ising_tile_cache_save(const char *path);
 si_status spring_ising_tile_cache_load(const char *path, int32_t *n_loaded);
 si_status spring_ising_tile_cache_clear(void);
 
-/* Readout: s[r*n + i] = +1 if q_i >= 0 (also -0.0), else -1 (device int8). */
+/* Readout: the spins are the signs of the final positions (Methods: the
+ * oscillators' positions are sampled as the Ising spins):
+ * s[r*n + i] = +1 if q_i >= 0 (also -0.0), else -1 (device int8). */
 si_status spring_ising_spins(si_ctx *ctx, int8_t *s);
 
 /* Eq. (1) energy of the current spins s = sign(q), per replica.
@@ -363,7 +369,8 @@ si_status spring_ising_update_best(si_ctx *ctx);
  * last set_state. */
 si_status spring_ising_get_best(si_ctx *ctx, double *best_e, int8_t *best_s);
 
-/* Energy trace of the in-run checks (si_params.energy_every = E > 0): copy
+/* Energy trace of the in-run checks (si_params.energy_every = E > 0; the
+ * Eq. (1) energy followed over the iterations, as in Fig. 4): copy
  * the rows recorded for the checks at steps E, 2E, ... <= t into e (device,
  * doubles, row k holding the energies of check k: r values, or n_inst*r on
  * a batch in the order of spring_ising_energy), and the number of rows to
