@@ -1,9 +1,12 @@
 // Host runtime of the Spring-Ising library: the C ABI declared in
 // include/spring_ising.h.  Owns the padded device buffers, builds the
 // zeta/Delta schedules, validates J, picks the step kernel and launches it.
+#include <errno.h>
 #include <math.h>
 #include <stdarg.h>
+#include <stdint.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <new>
@@ -1874,6 +1877,11 @@ si_status spring_ising_tile_cache_load(const char *path, int32_t *n_loaded) {
   while (fgets(line, sizeof line, f)) {
     ++lineno;
     const size_t len = strlen(line);
+    if (len == sizeof line - 1 && line[len - 1] != '\n' && !feof(f)) {
+      st = fail(SI_ERR_INVALID, "tile_cache_load: %s line %d: longer than %d characters", path,
+                lineno, (int)sizeof line - 2);
+      break;
+    }
     if (len && line[len - 1] == '\n') line[len - 1] = 0;
     if (lineno == 1) {
       if (strcmp(line, k_cache_magic) != 0) {
@@ -1896,18 +1904,39 @@ si_status spring_ising_tile_cache_load(const char *path, int32_t *n_loaded) {
       continue;
     }
     if (!line[0]) continue;
+    // eight whitespace-separated fields: seven decimal integers in int32
+    // range, then a finite non-negative time
     int v[7];
-    float us;
-    char extra;
-    if (sscanf(line, "%d %d %d %d %d %d %d %f %c", &v[0], &v[1], &v[2], &v[3], &v[4], &v[5],
-               &v[6], &us, &extra) != 8 ||
-        (v[0] != 0 && v[0] != 1) || v[1] < SI_PREC_FP32 || v[1] > SI_PREC_BF16X_MIXEDJ ||
-        v[2] < 0 || v[3] < 0 || v[4] < 64 || v[4] % 64 || v[5] < 1 ||
-        !tile_serves(v[0], v[1], v[6])) {
+    double us = -1.0;
+    int fields = 0;
+    bool ok = true;
+    char *cur = line;
+    while (ok) {
+      while (*cur == ' ' || *cur == '\t' || *cur == '\r') ++cur;
+      if (!*cur) break;
+      char *end = nullptr;
+      if (fields < 7) {
+        errno = 0;
+        const long long x = strtoll(cur, &end, 10);
+        ok = end != cur && errno == 0 && x >= INT32_MIN && x <= INT32_MAX;
+        if (ok) v[fields] = (int)x;
+      } else if (fields == 7) {
+        us = strtod(cur, &end);
+        ok = end != cur && isfinite(us) && us >= 0.0;
+      } else {
+        ok = false;
+      }
+      if (ok && *end && *end != ' ' && *end != '\t' && *end != '\r') ok = false;
+      cur = end;
+      ++fields;
+    }
+    if (!ok || fields != 8 || (v[0] != 0 && v[0] != 1) || v[1] < SI_PREC_FP32 ||
+        v[1] > SI_PREC_BF16X_MIXEDJ || v[2] < 0 || v[3] < 0 || v[4] < 64 || v[4] % 64 ||
+        v[5] < 1 || !tile_serves(v[0], v[1], v[6])) {
       st = fail(SI_ERR_INVALID, "tile_cache_load: %s line %d: bad entry", path, lineno);
       break;
     }
-    got[TileKey{v[0], v[1], v[2], v[3], v[4], v[5]}] = TileEntry{v[6], us};
+    got[TileKey{v[0], v[1], v[2], v[3], v[4], v[5]}] = TileEntry{v[6], (float)us};
   }
   if (st == SI_OK && lineno < 2) st = fail(SI_ERR_INVALID, "tile_cache_load: %s is incomplete", path);
   fclose(f);
