@@ -14,12 +14,15 @@ energy readout).  Reported value: spin-updates/s = N * R * iterations / s.
 Beside the headline line the same run is timed in the BF16 precision forms,
 and time-to-target-energy is measured: the target is the 1% quantile of the
 final energies of an FP32 run from other initial states; each form runs the
-same schedule with the exact energy of every replica checked every 50 steps
-(check cost included, timed with HIP events on the stream the kernels run
-on) and its time-to-target is the event time of the first check with a
-replica at or below the target.
+same schedule from five initial states with the exact energy of every
+replica checked every 50 steps on the device (check cost included, timed
+with HIP events on the stream the kernels run on); its time-to-target for
+an initial state is the event time of the first check with a replica at or
+below the target, and the form's figure is the median over the five.
 The precision form's full configurations (R = 2048: FP8 J at N = 2000, hi +
-lo BF16 J at N = 8000) are timed per step against FP32 on the same shapes.
+lo BF16 J at N = 8000) are timed per step against FP32 on the same shapes,
+and their time to target is measured with the same protocol over their
+5000-step schedule.
 The batched configuration (256 uneven instances, R = 64) is timed per step
 in FP32 and in the BF16 form (also as a graph replay), with a time to a
 per-instance target energy, and against the same instances stepped one
@@ -347,6 +350,32 @@ def precision_full_configurations(si, r=2048, total=5000, steps=200, warm=20):
     return out
 
 
+def precision_time_to_target(si, r=2048, total=5000):
+    """Time to target energy at the precision form's own configurations
+    (R = 2048, the 5000-step schedule): FP8 J against FP32 at N = 2000 (+-1
+    couplings, initial seeds 0-4, checks every 50 steps) and hi + lo BF16 J
+    against FP32 at N = 8000 (Gaussian couplings, seeds 0-2, checks every 100
+    steps, real-valued energies), with the protocol of time_to_target."""
+    import torch
+
+    from paper_2305_07187_amd import instances
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    out = {"replicas": r, "schedule_steps": total}
+    for key, n, kind, form, every, seeds in (("fp8j_n2000", 2000, "pm1", "bf16x_fp8j", 50, TTT_SEEDS),
+                                            ("hiloj_n8000", 8000, "gauss", "bf16x_hiloj", 100,
+                                             TTT_SEEDS[:3])):
+        J = instances.make_J_torch(n, kind, 0, dev)
+        rec = time_to_target(si, J, n, r, total, every, stream, 0, forms_timed=[form],
+                             seeds=seeds)
+        rec["n"] = n
+        rec["couplings"] = kind
+        out[key] = rec
+        del J
+        torch.cuda.synchronize()
+    return out
+
+
 def differentiation_form(si, n=2000, r=64, steps=2000, ckpt=100, repeats=3):
     """The differentiation configuration: gradient of the mean relaxed
     end-energy with respect to the 2000-entry Delta and zeta schedules at
@@ -422,7 +451,8 @@ TTT_SEEDS = (0, 1, 2, 3, 4)
 TTT_TARGET_SEED = 5
 
 
-def time_to_target(si, J, n, r, iters, every, stream, runs_per_form):
+def time_to_target(si, J, n, r, iters, every, stream, runs_per_form, forms_timed=None,
+                   seeds=TTT_SEEDS):
     """Time to target energy, BF16 forms against FP32, on the headline
     instance.  Target: the 1 % quantile (10th best of 1024) of the final
     energies of an FP32 run from initial positions of seed 5, so that no
@@ -438,7 +468,9 @@ def time_to_target(si, J, n, r, iters, every, stream, runs_per_form):
     fraction of replicas ending at or below the target, a trial costs its
     share t_run / R of a run of all R replicas together, and
     TTS99 = (t_run / R) ln(0.01) / ln(1 - P_s).  P_run = 1 - (1 - P_s)^R is
-    the chance that a whole run reaches the target."""
+    the chance that a whole run reaches the target.  forms_timed: the BF16
+    forms to compare (default all three); runs_per_form = 0 skips the
+    separate throughput runs without checks."""
     import math
 
     import numpy as np
@@ -453,17 +485,20 @@ def time_to_target(si, J, n, r, iters, every, stream, runs_per_form):
     e_ref = mref.energy(exact=bool(mref.info()["j_integer"])).cpu().numpy().astype(np.float64)
     mref.close()
     target = float(np.sort(e_ref)[max(0, int(0.01 * r) - 1)])
-    x0s = {sd: instances.make_x0_torch(n, r, sd, device=dev) for sd in TTT_SEEDS}
+    forms_timed = list(FORMS if forms_timed is None else forms_timed)
+    x0s = {sd: instances.make_x0_torch(n, r, sd, device=dev) for sd in seeds}
     forms, finals = {}, {}
-    for name in ["fp32"] + FORMS:
+    for name in ["fp32"] + forms_timed:
         # throughput of the form on full runs without in-run checks
-        plain = si.SpringIsing(J, x0s[0], total_steps=iters, precision=name)
-        el_tot, us, _ = timed_runs(plain, x0s[0], iters, runs_per_form, 1, stream)
-        plain.close()
-        m = si.SpringIsing(J, x0s[0], total_steps=iters, precision=name, energy_every=every)
+        el_tot, us = None, None
+        if runs_per_form > 0:
+            plain = si.SpringIsing(J, x0s[seeds[0]], total_steps=iters, precision=name)
+            el_tot, us, _ = timed_runs(plain, x0s[seeds[0]], iters, runs_per_form, 1, stream)
+            plain.close()
+        m = si.SpringIsing(J, x0s[seeds[0]], total_steps=iters, precision=name, energy_every=every)
         m.run(every)  # warm-up
         per_seed, pooled = [], []
-        for sd in TTT_SEEDS:
+        for sd in seeds:
             m.set_state(x0s[sd], None, 0)
             times = _chunked_run(m, every, checks, stream)
             tr = m.energy_trace().cpu().numpy()
@@ -487,14 +522,16 @@ def time_to_target(si, J, n, r, iters, every, stream, runs_per_form):
             tts99 = t_trial * math.log(0.01) / math.log(1.0 - p_s)
         else:
             tts99 = None
-        forms[name] = {"kernel": kernel, "spin_updates_per_s": n * r * iters * runs_per_form / el_tot,
+        forms[name] = {"kernel": kernel,
+                       "spin_updates_per_s": (n * r * iters * runs_per_form / el_tot
+                                              if el_tot else None),
                        "avg_launch_us": us,
                        "ttt_median_s": med if math.isfinite(med) else None,
                        "per_seed": per_seed, "run_with_checks_s": t_run,
                        "p_success": p_s, "p_run": 1.0 - (1.0 - p_s) ** r, "tts99_s": tts99,
                        "mean_energy": float(fin.mean()), "best_energy": float(fin.min())}
     t32 = forms["fp32"]["ttt_median_s"]
-    for name in FORMS:
+    for name in forms_timed:
         f = forms[name]
         f["ks_pvalue_vs_fp32"] = float(ks_2samp(finals[name], finals["fp32"]).pvalue)
         a, b = finals[name], finals["fp32"]
@@ -506,7 +543,7 @@ def time_to_target(si, J, n, r, iters, every, stream, runs_per_form):
         f["ttt_speedup_vs_fp32"] = (t32 / tf) if (t32 and tf) else None
         f["tts99_speedup_vs_fp32"] = (forms["fp32"]["tts99_s"] / f["tts99_s"]
                                       if (forms["fp32"]["tts99_s"] and f["tts99_s"]) else None)
-    return {"target_energy": target, "check_every": every, "seeds": list(TTT_SEEDS),
+    return {"target_energy": target, "check_every": every, "seeds": list(seeds),
             "target": f"1% quantile of the final energies of an FP32 run from initial "
                       f"positions of seed {TTT_TARGET_SEED}",
             "forms": forms}
@@ -646,6 +683,7 @@ def main():
     model.close()
     if fp32_line and not args.no_forms and (n, r, args.couplings) == (N, R, "pm1"):
         out["precision_full_configurations"] = precision_full_configurations(si)
+        out["precision_full_configurations"]["time_to_target"] = precision_time_to_target(si)
     if fp32_line and not args.no_batched and (n, r, args.couplings) == (N, R, "pm1"):
         out["batched_form"] = batched_form(si, steps=args.batched_steps,
                                            sequential=not args.no_sequential,
