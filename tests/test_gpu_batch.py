@@ -452,3 +452,33 @@ def test_batch_timeline(precision, btile):
     m.close()
     ref.close()
     b.close()
+
+
+@pytest.mark.parametrize("precision,btile", [("fp32", 1), ("fp32", 2), ("bf16x_mixedj", 1)])
+def test_batch_with_several_replica_tiles(precision, btile):
+    # R = 130 pads to three 64-replica column tiles: every instance has items
+    # in several columns, dealt to its XCD queue together
+    import torch
+    si = ensure_built()
+    announce(f"batch with R = 130 ({precision}, tile {btile}) vs standalone runs")
+    specs = [(300, "pm1"), (129, "gauss"), (64, "pm1"), (1000, "gauss"), (520, "pm1")]
+    r, S = 130, 40
+    b, Js, xs = _batch(specs, S, r=r, precision=precision, tile=btile)
+    b.run(S)
+    xb, pb, t = b.state()
+    torch.cuda.synchronize()
+    assert t == S
+    for i, (n, kind) in enumerate(specs):
+        if precision == "fp32":
+            m = si.SpringIsing(to_dev(Js[i]), to_dev(xs[i]), total_steps=S, tile=BATCH_TILE)
+        else:
+            form, tile = FORM_TILE[kind]
+            m = si.SpringIsing(to_dev(Js[i]), to_dev(xs[i]), total_steps=S, precision=form,
+                               tile=tile)
+        m.run(S)
+        x, p, _ = m.state()
+        torch.cuda.synchronize()
+        assert np.array_equal(x.cpu().numpy(), xb[i].cpu().numpy()), (i, n, kind)
+        assert np.array_equal(p.cpu().numpy(), pb[i].cpu().numpy()), (i, n, kind)
+        m.close()
+    b.close()
