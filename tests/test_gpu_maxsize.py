@@ -106,3 +106,37 @@ def test_sizes_beyond_the_limit_are_refused():
     rc = lib.spring_ising_init(ctypes.byref(ctx), 65537, 1, ctypes.c_void_p(J.data_ptr()),
                                ctypes.c_void_p(x.data_ptr()), None, ctypes.byref(prm), None)
     assert rc == si.SI_ERR_INVALID and not ctx.value
+
+
+@pytest.mark.parametrize("precision", ["bf16x_fp8j", "bf16x_bf16j", "bf16x_hiloj", "bf16x3_exactj"])
+def test_largest_n_precision_forms(precision):
+    # The same closed form through the BF16 matrix cores: +-1 couplings are
+    # exact in FP8 and BF16 (hi + lo: lo = 0), +-0.25 positions are exact in
+    # BF16 (three-plane split: lower planes 0), every product is exact and
+    # every FP32 partial sum is a multiple of 0.25 below 2^14, so one step
+    # has the FP32 form's closed-form values; 64-bit offsets throughout.
+    import torch
+    si = ensure_built()
+    n, r = 65536, 3
+    announce(f"largest N in {precision}: complete ferromagnet N={n} R={r}, one step")
+    J = _ferromagnet(n)
+    x = _signs(n, r, 5)
+    m = si.SpringIsing(J, torch.from_numpy(x).cuda(), total_steps=4, precision=precision)
+    del J
+    torch.cuda.empty_cache()
+    assert m.info()["n_pad"] >= n
+    m.step()
+    q, p, t = m.state()
+    torch.cuda.synchronize()
+    Q, P = _closed_form_step(x)
+    qg, pg = q.cpu().numpy().astype(np.float64), p.cpu().numpy().astype(np.float64)
+    assert t == 1 and np.array_equal(qg, Q)
+    F = x.astype(np.float64).sum(axis=1, keepdims=True) - x
+    bound = 2.0 ** -22 * float(DT) * (float(ZS) * np.abs(F) + 0.5 * np.abs(x)) + 2.0 ** -23 * np.abs(P)
+    err = np.abs(pg - P)
+    assert np.all(err <= bound), float((err / bound).max())
+    er = m.energy(exact=False).cpu().numpy()
+    s = np.where(qg < 0, -1, 1).sum(axis=1).astype(np.float64)
+    np.testing.assert_array_equal(er, -(s * s - n) / 2)
+    announce(f"  {m.info()['kernel_name']}: max momentum error {err.max():.2e}")
+    m.close()
