@@ -140,3 +140,44 @@ def test_largest_n_precision_forms(precision):
     np.testing.assert_array_equal(er, -(s * s - n) / 2)
     announce(f"  {m.info()['kernel_name']}: max momentum error {err.max():.2e}")
     m.close()
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x_mixedj"])
+def test_largest_n_in_a_batch(precision):
+    # a batch holding the largest instance beside a small one: the large
+    # member follows the closed form, the small one its standalone run
+    import torch
+    si = ensure_built()
+    n, r = 65536, 3
+    announce(f"largest N inside a batch ({precision})")
+    J = _ferromagnet(n)
+    x = _signs(n, r, 7)
+    Js = instances.make_pm1(100, 3)
+    xs = instances.make_x0(100, r, 3)
+    b = si.SpringIsingBatch([J, torch.from_numpy(Js).cuda()],
+                            [torch.from_numpy(x).cuda(), torch.from_numpy(xs).cuda()],
+                            total_steps=4, precision=precision)
+    del J
+    torch.cuda.empty_cache()
+    b.step()
+    qb, pb, t = b.state()
+    torch.cuda.synchronize()
+    Q, P = _closed_form_step(x)
+    qg, pg = qb[0].cpu().numpy().astype(np.float64), pb[0].cpu().numpy().astype(np.float64)
+    assert t == 1 and np.array_equal(qg, Q)
+    F = x.astype(np.float64).sum(axis=1, keepdims=True) - x
+    bound = 2.0 ** -22 * float(DT) * (float(ZS) * np.abs(F) + 0.5 * np.abs(x)) + 2.0 ** -23 * np.abs(P)
+    assert np.all(np.abs(pg - P) <= bound)
+    form, tile = ("fp32", 14) if precision == "fp32" else ("bf16x_fp8j", 9)
+    m = si.SpringIsing(torch.from_numpy(Js).cuda(), torch.from_numpy(xs).cuda(), total_steps=4,
+                       precision=form, tile=tile)
+    m.step()
+    q1, p1, _ = m.state()
+    torch.cuda.synchronize()
+    assert np.array_equal(q1.cpu().numpy(), qb[1].cpu().numpy())
+    assert np.array_equal(p1.cpu().numpy(), pb[1].cpu().numpy())
+    e = b.energy(exact=False)
+    s = np.where(qg < 0, -1, 1).sum(axis=1).astype(np.float64)
+    np.testing.assert_array_equal(e[0].cpu().numpy(), -(s * s - n) / 2)
+    m.close()
+    b.close()
