@@ -363,3 +363,26 @@ def test_checkpoint_interval_beyond_the_schedule():
     a = _grad(J, x0, dt, zeta, ckpt=S)
     b = _grad(J, x0, dt, zeta, ckpt=2 ** 30)
     assert a[0] == b[0] and np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
+
+
+def test_forward_half_at_the_end_of_the_schedule():
+    # with no steps left the loss is the relaxed energy of the current state
+    # and every gradient entry is zero
+    import torch
+    si = ensure_built()
+    announce("relaxed energy forward/backward with no steps left")
+    n, r, S = 100, 8, 20
+    J = instances.make_pm1(n, 6)
+    x0 = instances.make_x0(n, r, 6)
+    dt, zeta = _sched(1000, S)
+    m = si.SpringIsing(to_dev(J), to_dev(x0), total_steps=S)
+    m.set_schedule(to_dev(np.asarray(dt, np.float32)), to_dev(np.asarray(zeta, np.float32)))
+    m.run(S)
+    q, _, _ = m.state()
+    loss = m.relaxed_energy_forward(10)
+    g_dt, g_z = m.relaxed_energy_backward()
+    torch.cuda.synchronize()
+    want = oracle.relaxed_energy(J.astype(np.float64), q.cpu().numpy().T.astype(np.float64))
+    assert float(loss.cpu()[0]) == pytest.approx(want, rel=1e-5)  # J q in FP32
+    assert not g_dt.cpu().numpy().any() and not g_z.cpu().numpy().any()
+    m.close()

@@ -172,3 +172,33 @@ def test_in_run_checks_on_a_batch(precision):
                 oracle.ising_energy(Jn[i], bs[i].cpu().numpy().T.astype(np.int64)),
                 be[i].cpu().numpy())
     b.close()
+
+
+def test_in_run_checks_with_a_partial_last_interval():
+    # S not a multiple of E: checks at E, 2E, ... <= S only; E > S: no check
+    import torch
+    si = ensure_built()
+    announce("in-run energy checks with S % E != 0 and E > S")
+    n, r = 200, 8
+    J, x0 = to_dev(instances.make_pm1(n, 12)), to_dev(instances.make_x0(n, r, 12))
+    S, every = 107, 25
+    m = si.SpringIsing(J, x0, total_steps=S, energy_every=every)
+    m.run(S)
+    tr = m.energy_trace()
+    ref = si.SpringIsing(J, x0, total_steps=S)
+    rows = []
+    for k in range(S // every):
+        ref.run(every)
+        rows.append(ref.energy(exact=True).double())
+    torch.cuda.synchronize()
+    assert tr.shape == (S // every, r)
+    assert torch.equal(tr, torch.stack(rows))
+    ref.close()
+    m.close()
+    m = si.SpringIsing(J, x0, total_steps=S, energy_every=S + 1)
+    m.run(S)
+    assert m.energy_trace().shape == (0, r)
+    with pytest.raises(si.SpringIsingError) as e:
+        m.best()
+    assert e.value.status == si.SI_ERR_STATE
+    m.close()
