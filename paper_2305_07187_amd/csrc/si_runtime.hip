@@ -147,6 +147,7 @@ struct si_ctx {
   // split contraction: 0 = automatic, >= 1 = forced number of k ranges
   int32_t ksplit_mode = 0;
   int32_t user_tile = 0;        // tile requested at init (0: automatic)
+  int32_t table_tile = 0, table_split = 0;  // measured default for few replicas
   int32_t tile_source = SI_TILE_FROM_TABLE;
   int64_t b_items_cap = 0;      // int4 entries of the device work list
   unsigned long long *b_trace = nullptr;  // timeline records of traced steps
@@ -286,6 +287,7 @@ static int32_t split_for(const si_ctx *c, int32_t tile) {
   if (c->n_inst || c->qplanes || !tile_has_split(tile)) return 1;
   if (c->ksplit_mode >= 1) return c->ksplit_mode;
   if (c->user_tile != 0) return 1;
+  if (c->table_split > 0 && tile == c->table_tile) return c->table_split;
   const TileShape ts = tile_shape(tile);
   return auto_split((int64_t)(c->n_pad / ts.bm) * (c->r_pad / ts.bn), c->n, c->num_cus);
 }
@@ -351,6 +353,40 @@ static int32_t choose_tile_bf16(int32_t n, int32_t r, int num_cus, int32_t preci
     }
   }
   return best;
+}
+
+// Measured FP32 defaults for few replicas: the fastest (tile, contraction
+// split) of a sweep over every FP32 tile and split 1, 2, 4, 8 on MI355X at
+// N = 1000, 2000, 4000, 8000 and R = 32 .. 512, keyed by the N-bucket b
+// (2^(b-1) < N <= 2^b) and R rounded up to 64.  Against the size rule below
+// they run N = 8000, R = 64 in 83 us instead of 157 (J is streamed once per
+// step by 64-replica-wide tiles instead of twice, and the split fills the
+// chip), N = 4000, R = 64 in 28 us instead of 54, N = 2000, R = 128 in 18 us
+// instead of 28.
+struct FewReplicaDefault {
+  int32_t nb, r64, tile, split;
+};
+static const FewReplicaDefault k_few_replicas[] = {
+    {10, 64, 3, 4},  {10, 128, 3, 4},  {10, 256, 3, 2},  {10, 512, 3, 1},
+    {11, 64, 3, 4},  {11, 128, 14, 4}, {11, 256, 26, 4}, {11, 512, 23, 1},
+    {12, 64, 26, 8}, {12, 128, 26, 4}, {12, 256, 14, 2}, {12, 512, 34, 1},
+    {13, 64, 26, 4}, {13, 128, 26, 2}, {13, 256, 26, 1}, {13, 512, 1, 1},
+};
+
+static bool few_replica_default(int32_t n, int32_t r, int32_t *tile, int32_t *split) {
+  int32_t nb = 0;
+  while (nb < 31 && (1 << nb) < n) ++nb;
+  const int32_t r64 = (int32_t)round_up(r, 64);
+  for (const FewReplicaDefault &d : k_few_replicas)
+    if (d.nb == nb && d.r64 == r64) {
+      *tile = d.tile;
+      // a split needs at least 128 contraction entries per range
+      int32_t s = d.split;
+      while (s > 1 && s > round_up(n, 32) / 128) s /= 2;
+      *split = s;
+      return true;
+    }
+  return false;
 }
 
 static int32_t choose_tile(int32_t n, int32_t r, int num_cus) {
@@ -655,6 +691,9 @@ si_status spring_ising_init(si_ctx **out, int32_t n, int32_t r, const float *J, 
              tile_serves(0, prm->precision, cached)) {
     c->tile = cached;
     c->tile_source = SI_TILE_FROM_CACHE;
+  } else if (!lowp && c->num_cus == 256 &&
+             few_replica_default(n, r, &c->table_tile, &c->table_split)) {
+    c->tile = c->table_tile;
   } else {
     c->tile = lowp ? choose_tile_bf16(n, r, c->num_cus, prm->precision)
                    : choose_tile(n, r, c->num_cus);
